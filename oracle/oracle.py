@@ -1,0 +1,145 @@
+"""CPU oracle for batched affine-gap seed extension -- TEST INFRASTRUCTURE.
+
+Only the tests, the smoke check and the benchmark's CPU-baseline leg may
+import this module.  The product path (the HIP library and its binding)
+never imports, links or calls it.
+
+It wraps ``gotoh_oracle.c``: a plain scalar int64 implementation of the
+SALoBa paper's Eq. 1 (Section II-A), the affine-gap Smith-Waterman-Gotoh
+recurrence, returning per pair the highest cell score and its end position
+(first maximum in row-major order over target rows and query columns; see
+the header of the C file for every reading of the paper it takes).
+
+The shared library is compiled from the C source with gcc on first use
+(and by the repository's build step); it has no dependency on the GPU code.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "gotoh_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle_gotoh.so")
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the oracle shared library with gcc (-O2, plain scalar C)."""
+    if (not force and os.path.exists(_LIB)
+            and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)):
+        return _LIB
+    tmp = _LIB + ".tmp%d" % os.getpid()
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
+           "-o", tmp, _SRC]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is None:
+            build()
+            lib = ctypes.CDLL(_LIB)
+            i64 = ctypes.c_int64
+            p = ctypes.c_void_p
+            lib.oracle_align_batch.argtypes = [p, p, p, p, i64, i64, i64, i64,
+                                               i64, p, p, p, ctypes.c_int]
+            lib.oracle_align_batch.restype = ctypes.c_int
+            lib.oracle_cell_h.argtypes = [p, i64, i64, p, i64, i64, i64, i64,
+                                          i64, i64, i64, i64]
+            lib.oracle_cell_h.restype = i64
+            _lib = lib
+    return _lib
+
+
+def _ptr(a: np.ndarray) -> int:
+    return a.ctypes.data
+
+
+def default_threads() -> int:
+    try:
+        return max(1, len(os.sched_getaffinity(0)))
+    except AttributeError:  # pragma: no cover
+        return max(1, os.cpu_count() or 1)
+
+
+def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
+                nthreads: int | None = None):
+    """Oracle alignment of every pair.
+
+    q_seqs/t_seqs: uint8 arrays of 2-bit packed bases (4 per byte, LSB first).
+    q_offsets/t_offsets: int64 arrays of length n_pairs+1 (CSR, in bases).
+    scoring: (match, mismatch, gap_open, gap_extend); a gap of k bases costs
+    gap_open + k*gap_extend.
+    Returns (score, q_end, t_end) as int64 arrays.
+    """
+    lib = _load()
+    q_seqs = np.ascontiguousarray(q_seqs, dtype=np.uint8)
+    t_seqs = np.ascontiguousarray(t_seqs, dtype=np.uint8)
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.int64)
+    t_offsets = np.ascontiguousarray(t_offsets, dtype=np.int64)
+    n = len(q_offsets) - 1
+    if n < 0 or len(t_offsets) != n + 1:
+        raise ValueError("offset arrays must both have n_pairs+1 entries")
+    if n and (np.any(np.diff(q_offsets) < 0) or np.any(np.diff(t_offsets) < 0)):
+        raise ValueError("offsets must be non-decreasing")
+    if n and (q_offsets[-1] > 4 * len(q_seqs) or t_offsets[-1] > 4 * len(t_seqs)):
+        raise ValueError("offsets run past the packed buffers")
+    score = np.zeros(max(n, 0), dtype=np.int64)
+    qend = np.zeros(max(n, 0), dtype=np.int64)
+    tend = np.zeros(max(n, 0), dtype=np.int64)
+    if n == 0:
+        return score, qend, tend
+    # empty buffers still need a valid address
+    qb = q_seqs if len(q_seqs) else np.zeros(1, np.uint8)
+    tb = t_seqs if len(t_seqs) else np.zeros(1, np.uint8)
+    a, b, o, e = (int(x) for x in scoring)
+    rc = lib.oracle_align_batch(_ptr(qb), _ptr(q_offsets), _ptr(tb),
+                                _ptr(t_offsets), n, a, b, o, e, _ptr(score),
+                                _ptr(qend), _ptr(tend),
+                                int(nthreads or default_threads()))
+    if rc != 0:
+        raise MemoryError("oracle_align_batch failed (%d)" % rc)
+    return score, qend, tend
+
+
+def cell_h(q_seqs, q_start, m, t_seqs, t_start, n, scoring, ti, qj) -> int:
+    """H(ti, qj) of one pair's table (Eq. 1), or -1 outside the table."""
+    lib = _load()
+    q_seqs = np.ascontiguousarray(q_seqs, dtype=np.uint8)
+    t_seqs = np.ascontiguousarray(t_seqs, dtype=np.uint8)
+    a, b, o, e = (int(x) for x in scoring)
+    return int(lib.oracle_cell_h(_ptr(q_seqs), int(q_start), int(m),
+                                 _ptr(t_seqs), int(t_start), int(n),
+                                 a, b, o, e, int(ti), int(qj)))
+
+
+def align_strings(q: str, t: str, scoring=(1, -4, 6, 1)):
+    """Convenience for tests: align two ACGT strings, return (score, qend, tend)."""
+    qs, qo = _pack_strings([q])
+    ts, to = _pack_strings([t])
+    s, qe, te = align_batch(qs, qo, ts, to, scoring, nthreads=1)
+    return int(s[0]), int(qe[0]), int(te[0])
+
+
+def _pack_strings(seqs):
+    """Local 2-bit packer used only by align_strings (the oracle keeps its
+    own copy of the input convention; it shares no code with the generator)."""
+    code = {"A": 0, "C": 1, "G": 2, "T": 3}
+    bases = [code[c] for s in seqs for c in s.upper()]
+    offs = [0]
+    for s in seqs:
+        offs.append(offs[-1] + len(s))
+    nbytes = (len(bases) + 3) // 4
+    buf = bytearray(max(nbytes, 1))
+    for k, v in enumerate(bases):
+        buf[k >> 2] |= v << (2 * (k & 3))
+    return np.frombuffer(bytes(buf), dtype=np.uint8), np.array(offs, np.int64)
