@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Throughput benchmark of the batched seed-extension hot path on one GPU.
+
+One step = one salo_align_batch call over the whole synthetic batch (every
+pair's affine-gap Smith-Waterman-Gotoh table, Section II-A Eq. 1, plus its
+maximum and end position), inputs already resident in HBM.  Prints ONE JSON
+line.  The default workload is the short-read extension batch: 2,000,000
+pairs, query length U{50..250}, target = source + U{0..100} flank, 1%
+substitutions, 0.1% indels, 10% unrelated pairs, scoring (1, -4, 6, 1).
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
+                       [--workload short_reads|plain_small|long_uneven|mixed]
+                       [--mode auto|plain|persistent] [--lanes L --cols C]
+                       [--no-cpu-baseline] [--parity-sample N]
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "GCUPS (bit-exact vs oracle) on mixed-length batches; p50/p99 latency at fixed rate"
+SCORING = (1, -4, 6, 1)
+# Algorithmic integer operations per DP cell (Eq. 1): S select (2), diagonal
+# add (1), E (2), F (2), H = max of four (2), H - alpha (1), running max (1).
+OPS_PER_CELL = 11
+# gfx950 VALU: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do 2 elements.
+PEAK_TOPS = {"u16x2": 256 * 64 * 2.4e9 * 2 / 1e12, "i32": 256 * 64 * 2.4e9 / 1e12}
+
+
+def log(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="short_reads")
+    ap.add_argument("--pairs", type=int, default=0, help="override the pair count")
+    ap.add_argument("--mode", default="auto")
+    ap.add_argument("--lanes", type=int, default=0)
+    ap.add_argument("--cols", type=int, default=0)
+    ap.add_argument("--waves-per-cu", type=int, default=0)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--parity-sample", type=int, default=3000)
+    args = ap.parse_args(argv)
+
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build has no multi-GPU path "
+              "(pairs are independent; see DESIGN.md for how it would shard)",
+              file=sys.stderr)
+        return 2
+
+    import torch
+    from oracle import oracle as O
+    from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import salo
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    salo.load()
+    dev = torch.device("cuda:0")
+
+    gen = I.WORKLOADS[args.workload]
+    t0 = time.time()
+    batch = gen(0, args.pairs) if args.pairs else gen(0)
+    cells = batch.cells()
+    log("workload %s: %d pairs, %.3e cells, generated in %.1fs" % (
+        args.workload, batch.n_pairs, cells, time.time() - t0))
+
+    q, qo, t, to = salo.to_device(batch, dev)
+    n = batch.n_pairs
+    out = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(3))
+    opts = dict(mode=args.mode, lanes=args.lanes, cols=args.cols,
+                waves_per_cu=args.waves_per_cu)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
+    torch.cuda.synchronize()
+
+    # timed region: K steps between events recorded on the launch stream
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    per = []
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    ev0.record(stream)
+    for _ in range(args.steps):
+        e_a = torch.cuda.Event(enable_timing=True)
+        e_b = torch.cuda.Event(enable_timing=True)
+        e_a.record(stream)
+        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
+        e_b.record(stream)
+        per.append((e_a, e_b))
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    total_ms = ev0.elapsed_time(ev1)
+    step_ms = [a.elapsed_time(b) for a, b in per]
+    ms_per_step = total_ms / args.steps
+    gcups = cells * args.steps / (total_ms * 1e-3) / 1e9
+    log("steps: %s ms (wall %.3fs)" % (" ".join("%.2f" % x for x in step_ms), wall))
+
+    # parity on a sample of pairs (the full-size check lives in the tests)
+    rng = np.random.default_rng(1)
+    k = min(args.parity_sample, n)
+    idx = np.sort(rng.choice(n, size=k, replace=False))
+    got = [x.cpu().numpy()[idx].astype(np.int64) for x in out]
+    sub = batch.subset(idx)
+    want = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING)
+    parity_ok = all(np.array_equal(g, w) for g, w in zip(got, want))
+    log("parity on %d sampled pairs: %s" % (k, "bit-exact" if parity_ok else "MISMATCH"))
+
+    # roofline of the DP kernel: algorithmic int ops per launch / launch time
+    dtype = "u16x2"
+    kern_ms = float(np.mean(step_ms))
+    achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
+    peak = PEAK_TOPS[dtype]
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "kernel": "salo plain/persistent DP", "ops_per_cell": OPS_PER_CELL}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = min(args.cpu_sample, n)
+        sub = batch.subset(np.arange(m))
+        thr = O.default_threads()
+        c0 = time.perf_counter()
+        O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING,
+                      nthreads=thr)
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(sub.cells() / dt / 1e9, 4), "unit": "GCUPS", "cores": thr,
+               "kind": "oracle",
+               "sample": "first %d pairs of the %s batch (%.3e cells), %.1fs" % (
+                   m, args.workload, sub.cells(), dt)}
+
+    rec = {
+        "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": n, "cells": cells,
+                   "scoring": list(SCORING), "mode": args.mode, "lanes": args.lanes,
+                   "cols": args.cols, "parity": "bit-exact on %d sampled pairs" % k
+                   if parity_ok else "MISMATCH on sampled pairs"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(rec), flush=True)
+    return 0 if parity_ok else 1
+
+
+if __name__ == "__main__":
+    sys.exit(main())

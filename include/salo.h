@@ -1,0 +1,144 @@
+/*
+ * salo.h -- C ABI of the MI355X (gfx950) batched seed-extension library.
+ *
+ * The operation (SALoBa, arXiv 2301.09310, Section II-A, Eq. 1): for every
+ * (query, target) pair of a batch, fill the affine-gap Smith-Waterman-Gotoh
+ * table
+ *     H(i,j) = max{0, E(i,j), F(i,j), H(i-1,j-1) + S(i,j)}
+ *     E(i,j) = max{H(i,j-1) - alpha, E(i,j-1) - beta}
+ *     F(i,j) = max{H(i-1,j) - alpha, F(i-1,j) - beta}
+ * with i over target (reference) bases and j over query bases, and return
+ * the highest cell ("the highest score in the DP table", Section II-A) and
+ * its position.  Batches of pairs of uneven length are the workload of
+ * Section III-A (load imbalance) and Section V-D.
+ *
+ * Scoring (salo_scoring_t): S(i,j) = match when the bases are equal and
+ * mismatch otherwise; a gap of k bases costs gap_open + k*gap_extend, i.e.
+ * alpha = gap_open + gap_extend, beta = gap_extend.  Constraints:
+ * 1 <= match <= 32767, -32767 <= mismatch <= 0, 0 <= gap_open <= 32767,
+ * 0 <= gap_extend <= 32767.
+ *
+ * Sequence layout: bases A=0, C=1, G=2, T=3, 2 bits each, base k of a
+ * stream in byte k>>2 at bits 2*(k&3) (least significant pair first).
+ * q_seqs and t_seqs are two independent streams; pair p uses query bases
+ * [q_offsets[p], q_offsets[p+1]) and target bases
+ * [t_offsets[p], t_offsets[p+1]).  Offsets are int64, in bases, and need
+ * not be byte aligned.  Each stream pointer must be 4-byte aligned, its
+ * buffer readable up to the next multiple of 4 bytes past its last base,
+ * and hold at most 2^32-4 bytes.  Lengths are limited to 65535 bases.
+ *
+ * Results: out_score[p] >= 0; out_qend[p] / out_tend[p] are the 0-based
+ * query / target indices of the highest cell, the first one in row-major
+ * order (smallest target index, then smallest query index) when several
+ * cells tie; both are -1 when the score is 0.  A pair with invalid device
+ * data (decreasing offsets, or a length above 65535) gets -1 in all three
+ * outputs and is counted (salo_error_count).
+ *
+ * Memory and ownership: every pointer argument of the align calls is a
+ * DEVICE pointer on the current HIP device.  The caller owns inputs and
+ * outputs and keeps them alive until `stream` has passed the call; inputs
+ * are never written and the three outputs are fully overwritten.  The
+ * library owns a workspace per (device, stream), grown on demand outside
+ * stream capture (salo_reserve pre-sizes it).
+ *
+ * Errors and synchronisation: host-checkable errors return a negative
+ * status and enqueue nothing (NULL pointer with n_pairs > 0, n_pairs < 0,
+ * scoring out of range, misaligned stream pointer, n_pairs above 2^31-1);
+ * a failed HIP call returns SALO_ERR_HIP.  salo_last_error() gives a
+ * thread-local message for the last non-OK status.  n_pairs == 0 is a
+ * no-op.  The align calls are asynchronous: they only enqueue work on
+ * `stream` and never synchronise it.  Calls on different streams may run
+ * concurrently; calls that share a stream share its workspace in order.
+ */
+#ifndef SALO_H
+#define SALO_H
+
+#include <stdint.h>
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SALO_VERSION 1
+#define SALO_MAX_LEN 65535
+
+typedef struct {
+    int32_t match;       /* score of equal bases, > 0 */
+    int32_t mismatch;    /* score of unequal bases, <= 0 */
+    int32_t gap_open;    /* gap of k bases costs gap_open + k*gap_extend */
+    int32_t gap_extend;
+} salo_scoring_t;
+
+typedef enum {
+    SALO_OK = 0,
+    SALO_ERR_INVALID = -1,   /* bad argument (host-checkable) */
+    SALO_ERR_NOMEM = -2,     /* workspace allocation failed */
+    SALO_ERR_HIP = -3,       /* a HIP runtime call failed */
+    SALO_ERR_CAPTURE = -4,   /* workspace must grow while the stream is captured */
+    SALO_ERR_UNSUPPORTED = -5
+} salo_status_t;
+
+typedef enum {
+    SALO_MODE_AUTO = 0,        /* persistent, length-binned (the default) */
+    SALO_MODE_PLAIN = 1,       /* one launch, pairs in input order, fixed lanes/cols */
+    SALO_MODE_PERSISTENT = 2   /* one persistent launch over length bins */
+} salo_mode_t;
+
+typedef struct {
+    int32_t mode;           /* salo_mode_t */
+    int32_t lanes;          /* lanes per pair group (1,2,4,8,16,32,64); 0 = default */
+    int32_t cols;           /* query columns per lane (8 or 16); 0 = default */
+    int32_t force_int32;    /* 1: 32-bit cells for every pair */
+    int32_t waves_per_cu;   /* grid size in resident waves per CU; 0 = default */
+    int32_t reserved[3];    /* must be 0 */
+} salo_options_t;
+
+/*
+ * Align n_pairs pairs (Eq. 1 of Section II-A per pair) with default options.
+ * Arguments: packed query stream, its int64 offsets [n_pairs+1], packed
+ * target stream, its offsets [n_pairs+1], pair count, scoring, three int32
+ * output arrays [n_pairs], and the HIP stream to enqueue on.
+ */
+salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
+                               const uint8_t *t_seqs, const int64_t *t_offsets,
+                               int64_t n_pairs, salo_scoring_t scoring,
+                               int32_t *out_score, int32_t *out_qend,
+                               int32_t *out_tend, hipStream_t stream);
+
+/*
+ * As salo_align_batch, with explicit execution options (opts may be NULL).
+ * Every mode and every lanes/cols choice returns identical results; they
+ * differ only in how work is mapped to the GPU (Section IV-A's intra-query
+ * parallelism and Section IV-C's subwarp width are the lanes choice).
+ */
+salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                  const uint8_t *t_seqs, const int64_t *t_offsets,
+                                  int64_t n_pairs, salo_scoring_t scoring,
+                                  int32_t *out_score, int32_t *out_qend,
+                                  int32_t *out_tend, hipStream_t stream,
+                                  const salo_options_t *opts);
+
+/* Pre-size the workspace of (current device, stream) for batches of up to
+ * max_pairs pairs, so later calls allocate nothing (needed before graph
+ * capture).  Synchronous with respect to the host. */
+salo_status_t salo_reserve(int64_t max_pairs, hipStream_t stream);
+
+/* Number of invalid pairs seen on (current device, stream) since the last
+ * call; synchronises `stream`, then resets the counter. */
+salo_status_t salo_error_count(hipStream_t stream, int64_t *host_count);
+
+/* Message for the last non-OK status returned on this host thread. */
+const char *salo_last_error(void);
+
+/* Free every workspace the library holds (no call may be in flight). */
+void salo_release(void);
+
+/* SALO_VERSION of the loaded library. */
+int32_t salo_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SALO_H */

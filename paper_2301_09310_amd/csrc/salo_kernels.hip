@@ -1,0 +1,507 @@
+// gfx950 kernels for batched affine-gap seed extension.
+//
+// Operation (SALoBa, arXiv 2301.09310, Section II-A, Eq. 1): per pair, the
+// Smith-Waterman-Gotoh table over target rows i and query columns j, and
+// the first (row-major) cell holding its maximum.
+//
+// Mapping to CDNA4 (differs from the paper's CUDA design, Section IV):
+//  * A "group" of W lanes of a wave64 works on one pair (or two, see
+//    below) as a linear systolic array: lane l holds K query columns of the
+//    current chunk in VGPRs; target rows stream through the group; at step
+//    s lane l computes row s-l.  H and E of a lane's last column move to
+//    lane l+1 with one DPP row/wave shift (the paper passes them through
+//    shared memory, Section IV-A; it also found shuffles no faster,
+//    Section VII-A -- here the DPP move replaces both).  A chunk is W*K
+//    query columns; the group sweeps chunks left to right, and the last
+//    lane's column of a chunk (H and E for every row) is written to a
+//    per-wave global slot that lane 0 reads back, 4 rows ahead, for the
+//    next chunk (the role of the paper's lazy spill, Section IV-B).
+//  * Cells are 16-bit where a pair's score bound allows it: two pairs share
+//    a group, one in each half of every VGPR, and every DP operation is one
+//    packed instruction (v_pk_add_u16 / v_pk_sub_u16 clamp / v_pk_max_u16).
+//    E and F are clamped at 0; any E/F value <= 0 yields the same H, so
+//    unsigned saturating subtraction is exact.  The substitution score comes
+//    from one v_perm_b32 per cell pair: a per-row byte table (match -
+//    mismatch at the target base's slot) indexed by per-column query
+//    selectors.  Pairs outside the 16-bit bound use 32-bit cells, one pair
+//    per group.
+//  * Narrow groups (small W) are the paper's subwarps (Section IV-C):
+//    several pairs share a wave; the lanes-per-group choice trades the
+//    wavefront's ramp against column padding and per-wave imbalance.
+//  * End positions follow the first-maximum rule exactly: a lane keeps the
+//    highest row maximum of its columns with the first row reaching it
+//    (strict comparison), saves that row's H values to LDS when it
+//    improves, and at the end of a chunk finds the first column holding the
+//    maximum.  Candidates merge lexicographically (score, -row, -col)
+//    across chunks and then across the group's lanes.
+//
+// All lane-group counts and loop bounds of a unit are wave-uniform; units
+// never wait on one another, so every wave runs to completion on its own.
+#include "salo_internal.h"
+
+namespace salo {
+namespace {
+
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+
+__device__ __forceinline__ u16x2 as_v(uint32_t x) { return __builtin_bit_cast(u16x2, x); }
+__device__ __forceinline__ uint32_t as_u(u16x2 x) { return __builtin_bit_cast(uint32_t, x); }
+__device__ __forceinline__ uint32_t psub(uint32_t a, uint32_t b) {
+    return as_u(__builtin_elementwise_sub_sat(as_v(a), as_v(b)));
+}
+__device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
+    return as_u(as_v(a) + as_v(b));
+}
+__device__ __forceinline__ uint32_t pmax(uint32_t a, uint32_t b) {
+    return as_u(__builtin_elementwise_max(as_v(a), as_v(b)));
+}
+__device__ __forceinline__ int max3i(int a, int b, int c) {
+    return max(max(a, b), c);
+}
+
+constexpr int kWave = 64;
+constexpr int32_t kBufDword3 = 0x00020000;   // raw buffer descriptor, gfx9 family
+
+// A packed base stream behind a range-checked buffer descriptor: reads
+// outside [0, nbytes) return 0 instead of touching memory.
+struct BaseStream {
+    __amdgpu_buffer_rsrc_t rsrc;
+
+    __device__ void init(const uint8_t *p, const int64_t *off, int64_t n_pairs) {
+        int64_t bases = n_pairs > 0 ? off[n_pairs] : 0;
+        int64_t bytes = ((bases + 15) >> 4) << 2;          // whole 32-bit words
+        if (bytes < 0) bytes = 0;
+        if (bytes > 0xFFFFFFF0ll) bytes = 0xFFFFFFF0ll;
+        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), 0,
+                                                 (int)(uint32_t)bytes, kBufDword3);
+    }
+    __device__ __forceinline__ uint32_t word(int64_t w) const {
+        const uint32_t off = (w < 0 || w >= (int64_t(1) << 30)) ? 0xFFFFFFF0u
+                                                                : (uint32_t)w << 2;
+        return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, 0, 0);
+    }
+};
+
+// DPP moves of the value `v` from lane-1 to lane, with `bnd` at each
+// group's first lane.
+template <int W>
+__device__ __forceinline__ uint32_t shift_in(uint32_t v, uint32_t bnd, int l) {
+    if constexpr (W == 1) {
+        return bnd;
+    } else if constexpr (W == 16) {
+        // row_shr:1 -- lanes 0/16/32/48 have no source and keep `bnd`
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x111, 0xf, 0xf, false);
+    } else if constexpr (W == 64) {
+        // wave_shr:1 -- lane 0 keeps `bnd`
+        return (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x138, 0xf, 0xf, false);
+    } else if constexpr (W < 16) {
+        const uint32_t s =
+            (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x111, 0xf, 0xf, false);
+        return l == 0 ? bnd : s;
+    } else {  // W == 32
+        const uint32_t s =
+            (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x138, 0xf, 0xf, false);
+        return l == 0 ? bnd : s;
+    }
+}
+
+__device__ __forceinline__ int wave_max(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ uint64_t group_max_u64(uint64_t v, int W) {
+    for (int o = W >> 1; o >= 1; o >>= 1) {
+        const uint32_t lo = __shfl_xor((uint32_t)v, o, kWave);
+        const uint32_t hi = __shfl_xor((uint32_t)(v >> 32), o, kWave);
+        const uint64_t w = ((uint64_t)hi << 32) | lo;
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+struct PairRef {
+    int64_t q0, t0;
+    int32_t m, n;
+    int32_t id;       // original pair index, -1 when absent
+    bool invalid;
+};
+
+__device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, bool present) {
+    PairRef r{0, 0, 0, 0, -1, false};
+    if (!present || pos >= P.n_pairs) return r;
+    const int64_t p = P.order ? (int64_t)P.order[pos] : pos;
+    const int64_t q0 = P.q_off[p], q1 = P.q_off[p + 1];
+    const int64_t t0 = P.t_off[p], t1 = P.t_off[p + 1];
+    r.id = (int32_t)p;
+    const int64_t m = q1 - q0, n = t1 - t0;
+    if (m < 0 || n < 0 || m > SALO_MAX_LEN_DEV || n > SALO_MAX_LEN_DEV || q0 < 0 || t0 < 0) {
+        r.invalid = true;
+        return r;
+    }
+    r.q0 = q0; r.t0 = t0; r.m = (int32_t)m; r.n = (int32_t)n;
+    return r;
+}
+
+struct Best {
+    int32_t score, row, col;
+    __device__ void offer(int32_t s, int32_t r, int32_t c) {
+        if (s > score || (s == score && s > 0 && (r < row || (r == row && c < col)))) {
+            score = s; row = r; col = c;
+        }
+    }
+    __device__ uint64_t key() const {
+        if (score <= 0) return 0;
+        return ((uint64_t)(uint32_t)score << 32) | ((uint64_t)(0xFFFFu - (uint32_t)row) << 16) |
+               (uint64_t)(0xFFFFu - (uint32_t)col);
+    }
+};
+
+__device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr, uint64_t key) {
+    if (pr.id < 0) return;
+    if (pr.invalid) {
+        P.out_score[pr.id] = -1; P.out_qend[pr.id] = -1; P.out_tend[pr.id] = -1;
+        atomicAdd(P.errors, 1ull);
+        return;
+    }
+    const int32_t s = (int32_t)(key >> 32);
+    P.out_score[pr.id] = s;
+    P.out_qend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)(key & 0xFFFF)) : -1;
+    P.out_tend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF)) : -1;
+}
+
+// One unit: G = 64/W groups; each group aligns NPG pairs (2 packed, 1 wide).
+// pos0: first position (in processing order) of the unit's pairs.
+// gsel: -1 = all groups, else only group gsel is processed (used when the
+// unit's boundary columns do not fit a slot together).
+template <int W, int K, bool PK>
+__device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs, const BaseStream &ts,
+                         int64_t pos0, int gsel, uint32_t *slot, uint32_t *lds_saved) {
+    constexpr int G = kWave / W;
+    constexpr int NPG = PK ? 2 : 1;
+    static_assert(K % 4 == 0 && K <= 16, "K must be 4..16, multiple of 4");
+    const int lane = threadIdx.x & (kWave - 1);
+    const int g = lane / W;
+    const int l = lane % W;
+    const bool mine = gsel < 0 || g == gsel;
+
+    PairRef pr[NPG];
+#pragma unroll
+    for (int h = 0; h < NPG; ++h) pr[h] = load_pair(P, pos0 + (int64_t)g * NPG + h, mine);
+
+    int rmax = 0, mmax = 0;
+#pragma unroll
+    for (int h = 0; h < NPG; ++h) {
+        rmax = max(rmax, pr[h].n);
+        mmax = max(mmax, pr[h].m);
+    }
+    const int R = wave_max(rmax);
+    // no target rows: every score is 0 and no boundary row may be touched
+    const int Cw = wave_max((mmax + W * K - 1) / (W * K));
+    const int C = R > 0 ? Cw : 0;
+    const int Gs = gsel < 0 ? G : 1;
+    const int gs = gsel < 0 ? g : 0;
+
+    Best best[NPG];
+#pragma unroll
+    for (int h = 0; h < NPG; ++h) best[h] = Best{0, -1, -1};
+
+    // scoring constants
+    const int32_t a = P.match, b = P.mismatch;
+    const int32_t alpha = P.gap_open + P.gap_extend, beta = P.gap_extend;
+    const uint32_t KC = (uint32_t)(a - b);               // byte: match - mismatch
+    const uint32_t NB2 = (uint32_t)(-b) * 0x10001u;
+    const uint32_t AL2 = (uint32_t)alpha * 0x10001u;
+    const uint32_t BE2 = (uint32_t)beta * 0x10001u;
+
+    // per-lane target stream geometry (per pair of the group)
+    int64_t twi[NPG];
+    uint32_t tsh[NPG];
+#pragma unroll
+    for (int h = 0; h < NPG; ++h) {
+        const int64_t p0 = pr[h].t0 - l;
+        twi[h] = p0 >> 4;                    // floor for negatives
+        tsh[h] = (uint32_t)(p0 & 15) * 2u;
+    }
+
+    uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
+
+    for (int c = 0; c < C; ++c) {
+        const int col0 = c * W * K + l * K;
+        // query selectors (PK) or query bases (wide) of this lane's K columns
+        uint32_t SEL[K];
+        {
+            uint32_t qw[NPG];
+#pragma unroll
+            for (int h = 0; h < NPG; ++h) {
+                const int64_t p0 = pr[h].q0 + col0;
+                const uint32_t lo = qs.word(p0 >> 4), hi = qs.word((p0 >> 4) + 1);
+                qw[h] = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(p0 & 15) * 2u);
+            }
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                if constexpr (PK) {
+                    const uint32_t sA = (col0 + k < pr[0].m) ? ((qw[0] >> (2 * k)) & 3u) : 12u;
+                    const uint32_t sB = (col0 + k < pr[1].m) ? (4u + ((qw[1] >> (2 * k)) & 3u)) : 12u;
+                    SEL[k] = sA | (sB << 16) | 0x0C000C00u;
+                } else {
+                    SEL[k] = (col0 + k < pr[0].m) ? ((qw[0] >> (2 * k)) & 3u) : 5u;
+                }
+            }
+        }
+
+        uint32_t H[K], HA[K], F[K];
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            H[k] = 0; F[k] = 0;
+            HA[k] = PK ? 0u : (uint32_t)(-alpha);
+        }
+        uint32_t hprev = 0;           // H(i-1, col0-1)
+        uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
+        uint32_t cbest = 0;           // packed (or wide) best row maximum in this chunk
+        int32_t crow[NPG];
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) crow[h] = -1;
+
+        const bool have_bnd = c > 0;   // implies R >= 1 (C == 0 when R == 0)
+        const bool write_bnd = c + 1 < C;
+        uint2 fifo[4];
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            fifo[r] = make_uint2(0u, 0u);
+            if (have_bnd) {
+                const int rr = min(r, R - 1);
+                fifo[r] = *reinterpret_cast<const uint2 *>(slot + 2 * ((size_t)rr * Gs + gs));
+            }
+        }
+
+        const int S = R + W - 1;
+        uint32_t tw_lo[NPG], tw_hi[NPG];
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) {
+            tw_lo[h] = ts.word(twi[h]);
+            tw_hi[h] = ts.word(twi[h] + 1);
+        }
+        uint32_t tw[NPG];
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) tw[h] = 0;
+        for (int s0 = 0; s0 < S; s0 += 4) {
+            if ((s0 & 15) == 0) {
+                // the next 16 target bases of each pair, already in flight;
+                // start loading the 16 after them
+#pragma unroll
+                for (int h = 0; h < NPG; ++h) {
+                    tw[h] = __builtin_amdgcn_alignbit(tw_hi[h], tw_lo[h], tsh[h]);
+                    const int64_t wi = twi[h] + ((s0 + 16) >> 4);
+                    tw_lo[h] = ts.word(wi);
+                    tw_hi[h] = ts.word(wi + 1);
+                }
+            }
+            const uint32_t jsh = (uint32_t)(s0 & 15) * 2u;
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int s = s0 + j;
+                if (s < S) {
+                const int i = s - l;
+                const uint2 bnd = fifo[j & 3];
+                if (have_bnd) {
+                    const int rr = min(s + 4, R - 1);
+                    fifo[j & 3] = *reinterpret_cast<const uint2 *>(slot + 2 * ((size_t)rr * Gs + gs));
+                }
+                const uint32_t hin = shift_in<W>(hout, bnd.x, l);
+                const uint32_t ein = shift_in<W>(eout, bnd.y, l);
+                if (i >= 0 && i < R) {
+                    uint32_t e = ein;
+                    uint32_t hd = hprev;
+                    uint32_t rowmax = 0;
+                    if constexpr (PK) {
+                        const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
+                        const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
+                        const uint32_t TA = i < pr[0].n ? (KC << (bA << 3)) : 0u;
+                        const uint32_t TB = i < pr[1].n ? (KC << (bB << 3)) : 0u;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const uint32_t T = __builtin_amdgcn_perm(TB, TA, SEL[k]);
+                            const uint32_t d = psub(padd(hd, T), NB2);
+                            hd = H[k];
+                            const uint32_t f = pmax(psub(F[k], BE2), HA[k]);
+                            F[k] = f;
+                            const uint32_t hh = pmax(pmax(d, f), e);
+                            H[k] = hh;
+                            const uint32_t ha = psub(hh, AL2);
+                            HA[k] = ha;
+                            rowmax = k == 0 ? hh : pmax(rowmax, hh);
+                            e = pmax(psub(e, BE2), ha);
+                        }
+                    } else {
+                        const uint32_t tb = i < pr[0].n ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const int sc = SEL[k] == tb ? a : b;
+                            const int d = (int)hd + sc;
+                            hd = H[k];
+                            const int f = max3i((int)F[k] - beta, (int)HA[k], 0);
+                            F[k] = (uint32_t)f;
+                            const int hh = max3i(d, f, (int)e);
+                            H[k] = (uint32_t)hh;
+                            const int ha = hh - alpha;
+                            HA[k] = (uint32_t)ha;
+                            rowmax = k == 0 ? (uint32_t)hh : (uint32_t)max((int)rowmax, hh);
+                            e = (uint32_t)max3i((int)e - beta, ha, 0);
+                        }
+                    }
+                    hprev = hin;
+                    hout = H[K - 1];
+                    eout = e;
+                    // row-level tracking of the first maximum
+                    if constexpr (PK) {
+                        const uint32_t nb = pmax(cbest, rowmax);
+                        const uint32_t chg = nb ^ cbest;
+                        cbest = nb;
+                        if (chg & 0xFFFFu) {
+                            crow[0] = i;
+#pragma unroll
+                            for (int k = 0; k < K; k += 4)
+                                *reinterpret_cast<uint4 *>(my_saved + k) =
+                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                        }
+                        if (chg >> 16) {
+                            crow[1] = i;
+#pragma unroll
+                            for (int k = 0; k < K; k += 4)
+                                *reinterpret_cast<uint4 *>(my_saved + K + k) =
+                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                        }
+                    } else {
+                        if ((int)rowmax > (int)cbest) {
+                            cbest = rowmax;
+                            crow[0] = i;
+#pragma unroll
+                            for (int k = 0; k < K; k += 4)
+                                *reinterpret_cast<uint4 *>(my_saved + k) =
+                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                        }
+                    }
+                    if (write_bnd && l == W - 1 && mine)
+                        *reinterpret_cast<uint2 *>(slot + 2 * ((size_t)i * Gs + gs)) =
+                            make_uint2(hout, eout);
+                }
+                }  // s < S
+            }
+        }
+
+        // resolve this chunk's candidate column per pair
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) {
+            const uint32_t v = PK ? ((cbest >> (16 * h)) & 0xFFFFu) : cbest;
+            if ((int)v > 0) {
+                int kk = K - 1;
+#pragma unroll
+                for (int k = K - 1; k >= 0; --k) {
+                    const uint32_t hv = PK ? ((my_saved[h * K + k] >> (16 * h)) & 0xFFFFu)
+                                           : my_saved[k];
+                    if (hv == v) kk = k;
+                }
+                best[h].offer((int32_t)v, crow[h], col0 + kk);
+            }
+        }
+        // the slot's column becomes the next chunk's input: make the last
+        // lanes' stores visible to lane 0 of every group
+        __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+    }
+
+#pragma unroll
+    for (int h = 0; h < NPG; ++h) {
+        const uint64_t key = group_max_u64(best[h].key(), W);
+        if (l == 0 && mine) write_result(P, pr[h], key);
+    }
+}
+
+// A unit is packed-eligible when every pair's score bound stays below 2^15.
+template <int W>
+__device__ bool unit_packed_ok(const KParams &P, int64_t pos0, int npairs) {
+    if (!P.packed_ok || P.force_int32) return false;
+    const int lane = threadIdx.x & (kWave - 1);
+    bool ok = true;
+    for (int k = lane; k < npairs; k += kWave) {
+        const PairRef r = load_pair(P, pos0 + k, true);
+        if (r.id >= 0 && !r.invalid) {
+            const int64_t mn = min(r.m, r.n);
+            if ((int64_t)P.match * (mn + 1) - (int64_t)P.mismatch > 32767) ok = false;
+        }
+    }
+    return __builtin_amdgcn_readfirstlane(__ballot(!ok) == 0ull ? 1 : 0) != 0;
+}
+
+template <int W, int K>
+__device__ void process_unit(const KParams &P, const BaseStream &qs, const BaseStream &ts,
+                             int64_t pos0, int npairs, uint32_t *slot, uint32_t *lds) {
+    constexpr int G = kWave / W;
+    // rows one slot holds for G groups; larger units run one group at a time
+    int rmax = 0;
+    const int lane = threadIdx.x & (kWave - 1);
+    for (int k = lane; k < npairs; k += kWave) {
+        const PairRef r = load_pair(P, pos0 + k, true);
+        rmax = max(rmax, r.n);
+    }
+    const int R = wave_max(rmax);
+    // one call site per instantiation keeps run_unit inlined
+    const bool fits = (int64_t)R * G * 2 <= kSlotWords;
+    const int nsel = fits ? 1 : G;
+    if (unit_packed_ok<W>(P, pos0, npairs)) {
+        for (int gp = 0; gp < nsel; ++gp)
+            run_unit<W, K, true>(P, qs, ts, pos0, fits ? -1 : gp, slot, lds);
+    } else {
+        for (int it = 0; it < 2 * nsel; ++it) {
+            const int half = it / nsel, gp = it % nsel;
+            run_unit<W, K, false>(P, qs, ts, pos0 + (int64_t)half * G, fits ? -1 : gp, slot, lds);
+        }
+    }
+}
+
+// Plain mode: pairs in input order, fixed lanes/cols, units of 128/W pairs
+// dealt to waves round robin.
+template <int W, int K>
+__global__ __launch_bounds__(64) void plain_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
+    BaseStream qs, ts;
+    qs.init(P.q_seqs, P.q_off, P.n_pairs);
+    ts.init(P.t_seqs, P.t_off, P.n_pairs);
+    constexpr int PPU = 2 * (kWave / W);
+    const int64_t n_units = (P.n_pairs + PPU - 1) / PPU;
+    uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
+    for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
+        const int64_t pos0 = u * PPU;
+        const int np = (int)min<int64_t>(PPU, P.n_pairs - pos0);
+        process_unit<W, K>(P, qs, ts, pos0, np, slot, lds_saved);
+    }
+}
+
+}  // namespace
+
+#define SALO_PLAIN_VARIANTS(X) \
+    X(1, 16) X(2, 16) X(4, 16) X(8, 16) X(16, 16) X(32, 16) X(64, 16) \
+    X(2, 8) X(4, 8) X(8, 8) X(16, 8)
+
+bool plain_variant_exists(int lanes, int cols) {
+#define X(w, k) if (lanes == w && cols == k) return true;
+    SALO_PLAIN_VARIANTS(X)
+#undef X
+    return false;
+}
+
+hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid, hipStream_t stream) {
+#define X(w, k)                                                                 \
+    if (lanes == w && cols == k) {                                              \
+        hipLaunchKernelGGL((plain_kernel<w, k>), dim3(grid), dim3(kWave), 0,    \
+                           stream, p);                                          \
+        return hipGetLastError();                                               \
+    }
+    SALO_PLAIN_VARIANTS(X)
+#undef X
+    return hipErrorInvalidValue;
+}
+
+}  // namespace salo

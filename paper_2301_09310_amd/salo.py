@@ -1,0 +1,172 @@
+"""Thin Python binding of libsalo.so (argument marshalling only).
+
+Every alignment step runs in the library's gfx950 kernels; this module only
+turns torch tensors and streams into the pointers and sizes of the C ABI
+(include/salo.h) and raises on a non-OK status.  There is no fallback: if
+the library is missing, loading fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+PKG = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(PKG, "libsalo.so")
+
+MODE_AUTO, MODE_PLAIN, MODE_PERSISTENT = 0, 1, 2
+_MODES = {"auto": MODE_AUTO, "plain": MODE_PLAIN, "persistent": MODE_PERSISTENT}
+
+
+class SaloError(RuntimeError):
+    """A non-OK status from the library."""
+
+    def __init__(self, status: int, message: str):
+        super().__init__("salo status %d: %s" % (status, message))
+        self.status = status
+
+
+class Scoring(ctypes.Structure):
+    _fields_ = [("match", ctypes.c_int32), ("mismatch", ctypes.c_int32),
+                ("gap_open", ctypes.c_int32), ("gap_extend", ctypes.c_int32)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("mode", ctypes.c_int32), ("lanes", ctypes.c_int32),
+                ("cols", ctypes.c_int32), ("force_int32", ctypes.c_int32),
+                ("waves_per_cu", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 3)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+def load(path: str | None = None):
+    """Load libsalo.so (built by paper_2301_09310_amd.build)."""
+    global _lib
+    with _lock:
+        if _lib is not None and path is None:
+            return _lib
+        p = path or LIB_PATH
+        if not os.path.exists(p):
+            raise ImportError("libsalo.so not found at %s; build it with "
+                              "`python -m paper_2301_09310_amd.build`" % p)
+        lib = ctypes.CDLL(p)
+        vp, i64, i32 = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32
+        lib.salo_align_batch.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp]
+        lib.salo_align_batch.restype = i32
+        lib.salo_align_batch_ex.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp,
+                                            vp, ctypes.POINTER(Options)]
+        lib.salo_align_batch_ex.restype = i32
+        lib.salo_reserve.argtypes = [i64, vp]
+        lib.salo_reserve.restype = i32
+        lib.salo_error_count.argtypes = [vp, ctypes.POINTER(i64)]
+        lib.salo_error_count.restype = i32
+        lib.salo_last_error.argtypes = []
+        lib.salo_last_error.restype = ctypes.c_char_p
+        lib.salo_release.argtypes = []
+        lib.salo_release.restype = None
+        lib.salo_version.argtypes = []
+        lib.salo_version.restype = i32
+        if path is None:
+            _lib = lib
+        return lib
+
+
+def _check(lib, st: int):
+    if st != 0:
+        raise SaloError(st, lib.salo_last_error().decode())
+
+
+def _stream_handle(stream):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def make_options(mode="auto", lanes=0, cols=0, force_int32=False, waves_per_cu=0):
+    o = Options()
+    o.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
+    o.lanes, o.cols = int(lanes), int(cols)
+    o.force_int32 = 1 if force_int32 else 0
+    o.waves_per_cu = int(waves_per_cu)
+    return o
+
+
+def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
+                out=None, stream=None, **options):
+    """Align every pair on the GPU.
+
+    q_seqs/t_seqs: uint8 CUDA tensors (2-bit packed); q_offsets/t_offsets:
+    int64 CUDA tensors of n_pairs+1 entries.  Returns (score, q_end, t_end)
+    int32 CUDA tensors (or fills `out`, a triple of such tensors).  Keyword
+    options: mode ('auto' | 'plain' | 'persistent'), lanes, cols,
+    force_int32, waves_per_cu.
+    """
+    import torch
+    lib = load()
+    n = q_offsets.numel() - 1
+    if t_offsets.numel() - 1 != n:
+        raise ValueError("offset arrays differ in length")
+    for name, t, dt in (("q_seqs", q_seqs, torch.uint8), ("t_seqs", t_seqs, torch.uint8),
+                        ("q_offsets", q_offsets, torch.int64),
+                        ("t_offsets", t_offsets, torch.int64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, dt))
+    if out is None:
+        dev = q_offsets.device
+        out = tuple(torch.empty(max(n, 0), dtype=torch.int32, device=dev) for _ in range(3))
+    sc = Scoring(*[int(x) for x in scoring])
+    opts = make_options(**options)
+    st = lib.salo_align_batch_ex(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                                 t_offsets.data_ptr(), n, sc, out[0].data_ptr(),
+                                 out[1].data_ptr(), out[2].data_ptr(),
+                                 _stream_handle(stream), ctypes.byref(opts))
+    _check(lib, st)
+    return out
+
+
+def align_batch_raw(q_ptr, q_off_ptr, t_ptr, t_off_ptr, n_pairs, scoring, s_ptr, qe_ptr,
+                    te_ptr, stream_handle=None, options=None):
+    """Direct pass-through of salo_align_batch_ex with raw addresses;
+    returns the status code (no exception)."""
+    lib = load()
+    opts = options if options is not None else make_options()
+    return lib.salo_align_batch_ex(q_ptr, q_off_ptr, t_ptr, t_off_ptr, int(n_pairs),
+                                   Scoring(*[int(x) for x in scoring]), s_ptr, qe_ptr, te_ptr,
+                                   stream_handle, ctypes.byref(opts))
+
+
+def reserve(max_pairs: int, stream=None):
+    lib = load()
+    _check(lib, lib.salo_reserve(int(max_pairs), _stream_handle(stream)))
+
+
+def error_count(stream=None) -> int:
+    lib = load()
+    v = ctypes.c_int64(0)
+    _check(lib, lib.salo_error_count(_stream_handle(stream), ctypes.byref(v)))
+    return int(v.value)
+
+
+def last_error() -> str:
+    return load().salo_last_error().decode()
+
+
+def release():
+    load().salo_release()
+
+
+def version() -> int:
+    return int(load().salo_version())
+
+
+def to_device(batch, device="cuda"):
+    """Copy a packed inputs.Batch to device tensors (q, q_off, t, t_off)."""
+    import torch
+    return (torch.from_numpy(batch.q_seqs).to(device),
+            torch.from_numpy(batch.q_offsets).to(device),
+            torch.from_numpy(batch.t_seqs).to(device),
+            torch.from_numpy(batch.t_offsets).to(device))

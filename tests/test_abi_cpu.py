@@ -1,0 +1,92 @@
+"""C ABI checks that need no GPU: the library loads, exports every symbol
+include/salo.h declares, and host-side validation returns the documented
+status codes without touching a device."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2301_09310_amd import salo
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "salo.h")
+
+
+def _declared_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(salo_[a-z_0-9]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    if not os.path.exists(salo.LIB_PATH):
+        pytest.fail("libsalo.so is not built (python -m paper_2301_09310_amd.build)")
+    return salo.load()
+
+
+def test_header_declares_the_boundary():
+    names = _declared_functions()
+    for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
+              "salo_error_count", "salo_last_error", "salo_release", "salo_version"]:
+        assert n in names
+
+
+def test_every_declared_symbol_is_exported(lib):
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+
+
+def test_version(lib):
+    assert lib.salo_version() == 1
+
+
+SC = salo.Scoring(1, -4, 6, 1)
+NULL = ctypes.c_void_p(0)
+BUF = ctypes.create_string_buffer(64)
+ADDR = ctypes.addressof(BUF)
+
+
+def _call(n, sc=SC, ptr=ADDR, opts=None):
+    o = opts if opts is not None else salo.make_options()
+    return salo.load().salo_align_batch_ex(ptr, ptr, ptr, ptr, n, sc, ptr, ptr, ptr, NULL,
+                                           ctypes.byref(o))
+
+
+def test_zero_pairs_is_a_noop(lib):
+    assert _call(0, ptr=None) == 0
+
+
+def test_negative_count(lib):
+    assert _call(-1) == -1
+    assert "n_pairs" in lib.salo_last_error().decode()
+
+
+@pytest.mark.parametrize("sc", [(0, -4, 6, 1), (1, 1, 6, 1), (1, -4, -1, 1), (1, -4, 6, -2),
+                                (40000, -4, 6, 1), (1, -40000, 6, 1)])
+def test_bad_scoring(lib, sc):
+    assert _call(5, sc=salo.Scoring(*sc)) == -1
+
+
+def test_null_pointer(lib):
+    assert _call(5, ptr=None) == -1
+    assert "NULL" in lib.salo_last_error().decode()
+
+
+def test_misaligned_stream(lib):
+    assert _call(5, ptr=ADDR + 1) == -1
+    assert "aligned" in lib.salo_last_error().decode()
+
+
+def test_bad_options(lib):
+    o = salo.make_options()
+    o.reserved[1] = 3
+    assert _call(5, opts=o) == -1
+    o = salo.make_options()
+    o.mode = 9
+    assert _call(5, opts=o) == -1
+
+
+def test_too_many_pairs(lib):
+    assert _call(1 << 31) == -1

@@ -1,0 +1,161 @@
+"""GPU parity: the HIP library against the CPU oracle, bit-exact on every
+(score, q_end, t_end) -- the operation is integer-valued, so the tolerance
+is zero.  Every call goes through the C ABI (salo_align_batch_ex).
+
+Each test prints the case (workload, seed, options) before its GPU step."""
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2301_09310_amd import inputs as I
+
+pytestmark = pytest.mark.gpu
+
+SCORING = (1, -4, 6, 1)
+PLAIN_VARIANTS = [(1, 16), (2, 16), (4, 16), (8, 16), (16, 16), (32, 16), (64, 16),
+                  (2, 8), (4, 8), (8, 8), (16, 8)]
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+
+
+@pytest.fixture(scope="module")
+def dev():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2301_09310_amd import salo
+    salo.load()          # raises if the library is missing: no fallback
+    return torch.device("cuda:0")
+
+
+def gpu_align(batch, scoring=SCORING, **opts):
+    import torch
+    from paper_2301_09310_amd import salo
+    q, qo, t, to = salo.to_device(batch)
+    out = salo.align_batch(q, qo, t, to, scoring, **opts)
+    torch.cuda.synchronize()
+    return tuple(x.cpu().numpy().astype(np.int64) for x in out)
+
+
+def oracle_align(batch, scoring=SCORING):
+    return O.align_batch(batch.q_seqs, batch.q_offsets, batch.t_seqs, batch.t_offsets,
+                         scoring)
+
+
+def assert_same(batch, got, want, label):
+    names = ("score", "q_end", "t_end")
+    for k in range(3):
+        bad = np.nonzero(got[k] != want[k])[0]
+        if bad.size:
+            p = int(bad[0])
+            q, t = batch.pair_strings(p) if batch.q_lens()[p] < 400 else ("...", "...")
+            pytest.fail("%s: %d mismatches in %s; first pair %d (m=%d n=%d): gpu %s oracle %s"
+                        " q=%s t=%s" % (label, bad.size, names[k], p, batch.q_lens()[p],
+                                        batch.t_lens()[p],
+                                        tuple(int(g[p]) for g in got),
+                                        tuple(int(w[p]) for w in want), q, t))
+
+
+def test_plain_small_default(dev):
+    b = I.plain_small()
+    _say("plain_small seed 0, default options")
+    got = gpu_align(b)
+    assert_same(b, got, oracle_align(b), "plain_small")
+
+
+@pytest.mark.parametrize("lanes,cols", PLAIN_VARIANTS)
+def test_random_pairs_every_variant(dev, lanes, cols):
+    b = I.random_pairs(11, 600, 300)
+    want = oracle_align(b)
+    _say("random_pairs seed 11 plain lanes=%d cols=%d" % (lanes, cols))
+    assert_same(b, gpu_align(b, mode="plain", lanes=lanes, cols=cols), want,
+                "lanes=%d cols=%d" % (lanes, cols))
+    _say("random_pairs seed 11 plain lanes=%d cols=%d int32" % (lanes, cols))
+    assert_same(b, gpu_align(b, mode="plain", lanes=lanes, cols=cols, force_int32=True),
+                want, "lanes=%d cols=%d int32" % (lanes, cols))
+
+
+@pytest.mark.parametrize("scoring", [(1, -4, 6, 1), (2, -3, 5, 2), (1, -1, 1, 1),
+                                     (3, 0, 2, 1), (1, -2, 0, 1), (5, -4, 3, 0),
+                                     (1, -4, 0, 0), (200, -100, 50, 7), (7, -300, 12, 3)])
+def test_scorings(dev, scoring):
+    b = I.random_pairs(21, 400, 200)
+    want = oracle_align(b, scoring)
+    for lanes, cols in [(4, 16), (16, 8)]:
+        _say("random_pairs seed 21 scoring", scoring, "lanes", lanes, "cols", cols)
+        assert_same(b, gpu_align(b, scoring, mode="plain", lanes=lanes, cols=cols), want,
+                    "scoring %s" % (scoring,))
+
+
+def _edge_batch():
+    rng = np.random.default_rng(5)
+    qs, ts = [], []
+    # empty and tiny
+    for m, n in [(0, 0), (0, 5), (5, 0), (1, 1), (1, 7), (7, 1), (2, 2)]:
+        qs.append(rng.integers(0, 4, m, dtype=np.uint8))
+        ts.append(rng.integers(0, 4, n, dtype=np.uint8))
+    # lengths around chunk widths (lanes*cols for several variants) and rows
+    for L in [7, 8, 9, 15, 16, 17, 31, 32, 33, 63, 64, 65, 127, 128, 129, 255, 256, 257,
+              1023, 1024, 1025]:
+        t = rng.integers(0, 4, L + 3, dtype=np.uint8)
+        qs.append(t[2:2 + L].copy())
+        ts.append(t)
+        qs.append(rng.integers(0, 4, L, dtype=np.uint8))
+        ts.append(rng.integers(0, 4, max(1, L // 3), dtype=np.uint8))
+    # tie-heavy: homopolymers and two-letter alphabets
+    for L in [5, 40, 150]:
+        qs.append(np.zeros(L, np.uint8)); ts.append(np.zeros(L + 7, np.uint8))
+        qs.append(rng.integers(0, 2, L, dtype=np.uint8))
+        ts.append(rng.integers(0, 2, 2 * L, dtype=np.uint8))
+    # very uneven shapes
+    qs.append(rng.integers(0, 4, 1500, dtype=np.uint8)); ts.append(rng.integers(0, 4, 9, dtype=np.uint8))
+    qs.append(rng.integers(0, 4, 9, dtype=np.uint8)); ts.append(rng.integers(0, 4, 3000, dtype=np.uint8))
+    # identical long strings (score = length)
+    s = rng.integers(0, 4, 2000, dtype=np.uint8)
+    qs.append(s.copy()); ts.append(s.copy())
+    return I.from_codes(qs, ts)
+
+
+def test_edge_cases(dev):
+    b = _edge_batch()
+    want = oracle_align(b)
+    assert want[0][-1] == 2000
+    for lanes, cols in PLAIN_VARIANTS:
+        _say("edge cases lanes=%d cols=%d" % (lanes, cols))
+        assert_same(b, gpu_align(b, mode="plain", lanes=lanes, cols=cols), want,
+                    "edges lanes=%d cols=%d" % (lanes, cols))
+    _say("edge cases default")
+    assert_same(b, gpu_align(b), want, "edges default")
+
+
+def test_int32_forced_by_score_bound(dev):
+    """match=16 puts long pairs above the 16-bit bound (16*(min+1) > 32767)."""
+    b = I.long_uneven(0, 60)
+    sc = (16, -20, 30, 5)
+    want = oracle_align(b, sc)
+    assert int(want[0].max()) > 32767
+    _say("long_uneven 60 pairs scoring", sc)
+    assert_same(b, gpu_align(b, sc), want, "int32 by bound")
+
+
+def test_invalid_pairs_are_flagged(dev):
+    import torch
+    from paper_2301_09310_amd import salo
+    b = I.random_pairs(3, 40, 50)
+    qo = b.q_offsets.copy()
+    qo[10] = qo[11] + 5              # pair 10 gets a negative length (pair 9 a longer one)
+    to = b.t_offsets.copy()
+    to[21] = to[20] + 70000          # pair 20 gets a target above 65535 bases, 21 a negative one
+    bad = I.Batch(b.q_seqs, qo, b.t_seqs, to)
+    salo.error_count()               # reset
+    _say("invalid pairs")
+    got = gpu_align(bad)
+    for p in (10, 20, 21):
+        assert got[0][p] == -1 and got[1][p] == -1 and got[2][p] == -1
+    assert salo.error_count() == 3
+    want = oracle_align(b)
+    ok = [p for p in range(40) if p not in (9, 10, 20, 21)]
+    for k in range(3):
+        assert np.array_equal(got[k][ok], want[k][ok])
