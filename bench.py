@@ -51,8 +51,10 @@ def main(argv=None) -> int:
     ap.add_argument("--cols", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=200_000)
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--parity-sample", type=int, default=3000)
+    ap.add_argument("--compare-plain", action="store_true")
+    ap.add_argument("--plain-lanes", type=int, default=4)
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -90,28 +92,49 @@ def main(argv=None) -> int:
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
     torch.cuda.synchronize()
 
-    # timed region: K steps between events recorded on the launch stream
+    # timed region: K steps between events recorded on the launch stream;
+    # the library also records events around its plan and DP kernels
     ev0 = torch.cuda.Event(enable_timing=True)
     ev1 = torch.cuda.Event(enable_timing=True)
-    per = []
+    plan_ms, dp_ms = [], []
     torch.cuda.synchronize()
     wall0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
-        e_a = torch.cuda.Event(enable_timing=True)
-        e_b = torch.cuda.Event(enable_timing=True)
-        e_a.record(stream)
-        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
-        e_b.record(stream)
-        per.append((e_a, e_b))
+        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, timing=True, **opts)
+        a, b = salo.last_timing(stream)
+        plan_ms.append(a)
+        dp_ms.append(b)
     ev1.record(stream)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = ev0.elapsed_time(ev1)
-    step_ms = [a.elapsed_time(b) for a, b in per]
     ms_per_step = total_ms / args.steps
     gcups = cells * args.steps / (total_ms * 1e-3) / 1e9
-    log("steps: %s ms (wall %.3fs)" % (" ".join("%.2f" % x for x in step_ms), wall))
+    log("plan ms: %s" % " ".join("%.3f" % x for x in plan_ms))
+    log("dp ms:   %s (wall %.3fs)" % (" ".join("%.2f" % x for x in dp_ms), wall))
+
+    comparison = None
+    if args.compare_plain and args.mode != "plain":
+        popts = dict(mode="plain", lanes=args.plain_lanes, cols=16,
+                     waves_per_cu=args.waves_per_cu)
+        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        pm = e0.elapsed_time(e1) / args.steps
+        comparison = {"plain_gcups": round(cells / (pm * 1e-3) / 1e9, 2),
+                      "plain_ms_per_step": round(pm, 4), "plain_lanes": args.plain_lanes,
+                      "speedup_vs_plain": round(pm / ms_per_step, 3)}
+        log("plain lanes=%d: %.2f ms/step" % (args.plain_lanes, pm))
+        # the persistent outputs must be what the parity sample checks
+        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
+        torch.cuda.synchronize()
 
     # parity on a sample of pairs (the full-size check lives in the tests)
     rng = np.random.default_rng(1)
@@ -125,12 +148,13 @@ def main(argv=None) -> int:
 
     # roofline of the DP kernel: algorithmic int ops per launch / launch time
     dtype = "u16x2"
-    kern_ms = float(np.mean(step_ms))
+    kern_ms = float(np.mean(dp_ms))
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TOPS[dtype]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
             "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
-            "kernel": "salo plain/persistent DP", "ops_per_cell": OPS_PER_CELL}
+            "kernel": ("plain_kernel" if args.mode == "plain" else "persistent_kernel"),
+            "kernel_ms": round(kern_ms, 4), "ops_per_cell": OPS_PER_CELL}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -154,9 +178,12 @@ def main(argv=None) -> int:
         "config": {"workload": args.workload, "pairs": n, "cells": cells,
                    "scoring": list(SCORING), "mode": args.mode, "lanes": args.lanes,
                    "cols": args.cols, "parity": "bit-exact on %d sampled pairs" % k
-                   if parity_ok else "MISMATCH on sampled pairs"},
+                   if parity_ok else "MISMATCH on sampled pairs",
+                   "plan_ms": round(float(np.mean(plan_ms)), 4),
+                   "dp_ms": round(kern_ms, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
+        "comparison": comparison,
     }
     print(json.dumps(rec), flush=True)
     return 0 if parity_ok else 1

@@ -91,7 +91,9 @@ typedef struct {
     int32_t cols;           /* query columns per lane (8 or 16); 0 = default */
     int32_t force_int32;    /* 1: 32-bit cells for every pair */
     int32_t waves_per_cu;   /* grid size in resident waves per CU; 0 = default */
-    int32_t reserved[3];    /* must be 0 */
+    int32_t timing;         /* 1: record events around the plan and DP kernels
+                               (see salo_last_timing); 0 = off */
+    int32_t reserved[2];    /* must be 0 */
 } salo_options_t;
 
 /*
@@ -127,6 +129,13 @@ salo_status_t salo_reserve(int64_t max_pairs, hipStream_t stream);
 /* Number of invalid pairs seen on (current device, stream) since the last
  * call; synchronises `stream`, then resets the counter. */
 salo_status_t salo_error_count(hipStream_t stream, int64_t *host_count);
+
+/* Durations of the last align call on (current device, stream) that ran
+ * with opts->timing = 1: the planning kernels (binning and sorting; 0 in
+ * plain mode) and the DP kernel, in milliseconds, from HIP events recorded
+ * on `stream` around those launches.  Synchronises on the events.  Returns
+ * SALO_ERR_INVALID when no timed call has run on that stream. */
+salo_status_t salo_last_timing(hipStream_t stream, float *plan_ms, float *dp_ms);
 
 /* Message for the last non-OK status returned on this host thread. */
 const char *salo_last_error(void);

@@ -33,6 +33,17 @@ struct Workspace {
     unsigned long long *errors = nullptr;
     BinDesc *bins = nullptr;
     int32_t *counters = nullptr;        // [0] unit counter, [1] total units
+    // plan buffers of the persistent mode
+    int64_t plan_cap = 0;               // pairs the plan buffers hold
+    uint16_t *keys = nullptr;
+    int32_t *order = nullptr;
+    uint32_t *hist = nullptr;
+    uint32_t *block_sums = nullptr;
+    int32_t *binstat = nullptr;
+    // optional timing events: [0] before plan, [1] before DP, [2] after DP
+    hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
+    bool timed = false;
+    bool timed_plan = false;
 };
 
 std::mutex g_mu;
@@ -75,7 +86,7 @@ salo_status_t ensure_slots(Workspace &ws, int64_t slots, hipStream_t stream) {
     if (ws.slab) {
         hipError_t e = hipStreamSynchronize(stream);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        hipFree(ws.slab);
+        (void)hipFree(ws.slab);
         ws.slab = nullptr;
         ws.slots = 0;
     }
@@ -87,6 +98,53 @@ salo_status_t ensure_slots(Workspace &ws, int64_t slots, hipStream_t stream) {
     }
     ws.slots = slots;
     return SALO_OK;
+}
+
+salo_status_t ensure_plan(Workspace &ws, int64_t n_pairs, hipStream_t stream) {
+    if (ws.plan_cap >= n_pairs && ws.hist) return SALO_OK;
+    if (capturing(stream))
+        return fail(SALO_ERR_CAPTURE, "plan buffers must grow during stream capture; "
+                                      "call salo_reserve first");
+    if (ws.keys || ws.hist) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        (void)hipFree(ws.keys);
+        (void)hipFree(ws.order);
+        ws.keys = nullptr;
+        ws.order = nullptr;
+    }
+    const int64_t cap = n_pairs < 1024 ? 1024 : n_pairs;
+    if (hipMalloc(&ws.keys, sizeof(uint16_t) * cap) != hipSuccess ||
+        hipMalloc(&ws.order, sizeof(int32_t) * cap) != hipSuccess) {
+        ws.plan_cap = 0;
+        return fail(SALO_ERR_NOMEM, "workspace: plan buffers");
+    }
+    if (!ws.hist) {
+        if (hipMalloc(&ws.hist, sizeof(uint32_t) * kHistEntries) != hipSuccess ||
+            hipMalloc(&ws.block_sums, sizeof(uint32_t) * kScanBlocks) != hipSuccess ||
+            hipMalloc(&ws.binstat, sizeof(int32_t) * 3 * kMaxBins) != hipSuccess)
+            return fail(SALO_ERR_NOMEM, "workspace: plan histogram");
+    }
+    ws.plan_cap = cap;
+    return SALO_OK;
+}
+
+// Default length bins (query length upper bounds) and lane-group widths.
+// 16-bit bins first, then 32-bit bins; K = 16 query columns per lane.
+BinTable default_bins(int cols, int forced_lanes) {
+    BinTable bt;
+    std::memset(&bt, 0, sizeof bt);
+    const int32_t m_hi[] = {96, 200, 400, 1000, 3000, 65535, 1000, 65535};
+    const int32_t packed[] = {1, 1, 1, 1, 1, 1, 0, 0};
+    const int32_t lanes[] = {2, 2, 4, 8, 16, 32, 4, 16};
+    bt.n_bins = 8;
+    for (int b = 0; b < 8; ++b) {
+        bt.m_hi[b] = m_hi[b];
+        bt.packed[b] = packed[b];
+        bt.lanes[b] = forced_lanes ? forced_lanes : lanes[b];
+        bt.cols[b] = cols;
+    }
+    return bt;
 }
 
 salo_status_t validate(const uint8_t *q_seqs, const int64_t *q_offsets, const uint8_t *t_seqs,
@@ -165,16 +223,52 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
     p.unit_counter = ws->counters;
     p.total_units = ws->counters + 1;
 
-    // Until the binned persistent path lands, every mode runs the plain kernel.
-    const int lanes = o.lanes ? o.lanes : 4;
+    if (o.timing) {
+        for (auto &ev : ws->ev)
+            if (!ev && hipEventCreate(&ev) != hipSuccess)
+                return fail(SALO_ERR_HIP, "hipEventCreate");
+        ws->timed = true;
+        ws->timed_plan = o.mode != SALO_MODE_PLAIN;
+        if (hipEventRecord(ws->ev[0], stream) != hipSuccess)
+            return fail(SALO_ERR_HIP, "hipEventRecord");
+    }
+    auto mark = [&](int k) -> salo_status_t {
+        if (o.timing && hipEventRecord(ws->ev[k], stream) != hipSuccess)
+            return fail(SALO_ERR_HIP, "hipEventRecord");
+        return SALO_OK;
+    };
+
+    if (o.mode == SALO_MODE_PLAIN) {
+        const int lanes = o.lanes ? o.lanes : 4;
+        const int cols = o.cols ? o.cols : 16;
+        if (!plain_variant_exists(lanes, cols))
+            return fail(SALO_ERR_UNSUPPORTED, "no plain kernel for lanes=" +
+                                                  std::to_string(lanes) + " cols=" +
+                                                  std::to_string(cols));
+        if ((st = mark(1)) != SALO_OK) return st;
+        hipError_t e = launch_plain(p, lanes, cols, (int)grid, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch plain kernel");
+        return mark(2);
+    }
+
+    // persistent, length-binned
     const int cols = o.cols ? o.cols : 16;
-    if (!plain_variant_exists(lanes, cols))
-        return fail(SALO_ERR_UNSUPPORTED, "no kernel variant for lanes=" +
-                                              std::to_string(lanes) + " cols=" +
-                                              std::to_string(cols));
-    hipError_t e = launch_plain(p, lanes, cols, (int)grid, stream);
-    if (e != hipSuccess) return hip_fail(e, "launch plain kernel");
-    return SALO_OK;
+    if (cols != 8 && cols != 16)
+        return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports cols 8 or 16");
+    if (o.lanes && !persistent_lanes_supported(o.lanes))
+        return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports lanes 2..64");
+    st = ensure_plan(*ws, n_pairs, stream);
+    if (st != SALO_OK) return st;
+    const BinTable bt = default_bins(cols, o.lanes);
+    p.n_bins = bt.n_bins;
+    PlanBuffers pb{ws->keys, ws->order, ws->hist, ws->block_sums, ws->binstat};
+    hipError_t e = launch_plan(p, bt, pb, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch plan kernels");
+    p.order = ws->order;
+    if ((st = mark(1)) != SALO_OK) return st;
+    e = launch_persistent(p, cols, (int)grid, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch persistent kernel");
+    return mark(2);
 }
 
 salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
@@ -190,7 +284,9 @@ salo_status_t salo_reserve(int64_t max_pairs, hipStream_t stream) {
     Workspace *ws = nullptr;
     salo_status_t st = get_workspace(stream, &ws);
     if (st != SALO_OK) return st;
-    return ensure_slots(*ws, (int64_t)ws->cus * 8, stream);
+    st = ensure_slots(*ws, (int64_t)ws->cus * 8, stream);
+    if (st != SALO_OK) return st;
+    return ensure_plan(*ws, max_pairs, stream);
 }
 
 salo_status_t salo_error_count(hipStream_t stream, int64_t *host_count) {
@@ -211,6 +307,23 @@ salo_status_t salo_error_count(hipStream_t stream, int64_t *host_count) {
     return SALO_OK;
 }
 
+salo_status_t salo_last_timing(hipStream_t stream, float *plan_ms, float *dp_ms) {
+    if (!plan_ms || !dp_ms) return fail(SALO_ERR_INVALID, "NULL output pointer");
+    Workspace *ws = nullptr;
+    salo_status_t st = get_workspace(stream, &ws);
+    if (st != SALO_OK) return st;
+    if (!ws->timed) return fail(SALO_ERR_INVALID, "no timed call on this stream");
+    hipError_t e = hipEventSynchronize(ws->ev[2]);
+    if (e != hipSuccess) return hip_fail(e, "hipEventSynchronize");
+    float a = 0.f, b = 0.f;
+    if ((e = hipEventElapsedTime(&a, ws->ev[0], ws->ev[1])) != hipSuccess ||
+        (e = hipEventElapsedTime(&b, ws->ev[1], ws->ev[2])) != hipSuccess)
+        return hip_fail(e, "hipEventElapsedTime");
+    *plan_ms = ws->timed_plan ? a : 0.f;
+    *dp_ms = b;
+    return SALO_OK;
+}
+
 const char *salo_last_error(void) { return g_last_error.c_str(); }
 
 void salo_release(void) {
@@ -218,14 +331,21 @@ void salo_release(void) {
     for (auto &kv : g_ws) {
         Workspace &ws = kv.second;
         int cur = 0;
-        hipGetDevice(&cur);
-        hipSetDevice(ws.device);
-        hipDeviceSynchronize();
-        if (ws.slab) hipFree(ws.slab);
-        if (ws.errors) hipFree(ws.errors);
-        if (ws.bins) hipFree(ws.bins);
-        if (ws.counters) hipFree(ws.counters);
-        hipSetDevice(cur);
+        (void)hipGetDevice(&cur);
+        (void)hipSetDevice(ws.device);
+        (void)hipDeviceSynchronize();
+        (void)hipFree(ws.slab);
+        (void)hipFree(ws.errors);
+        (void)hipFree(ws.bins);
+        (void)hipFree(ws.counters);
+        (void)hipFree(ws.keys);
+        (void)hipFree(ws.order);
+        (void)hipFree(ws.hist);
+        (void)hipFree(ws.block_sums);
+        (void)hipFree(ws.binstat);
+        for (auto ev : ws.ev)
+            if (ev) (void)hipEventDestroy(ev);
+        (void)hipSetDevice(cur);
     }
     g_ws.clear();
 }

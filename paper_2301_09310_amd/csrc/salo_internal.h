@@ -17,16 +17,40 @@ constexpr int64_t kSlotWords = kSlotBytes / 4;
 constexpr int kMaxBins = 8;
 constexpr int64_t SALO_MAX_LEN_DEV = 65535;
 
+// One length bin: the pairs whose query length falls in (m_lo, m_hi] and
+// whose score bound does (packed) or does not (wide) admit 16-bit cells.
 struct BinDesc {
     int32_t lanes;        // lanes per pair group
     int32_t cols;         // query columns per lane
     int32_t packed;       // 1: 16-bit packed cells, 2 pairs per group
-    int32_t pairs;        // pairs per unit
-    int32_t count;        // pairs in this bin (device-written)
-    int32_t first;        // first position of the bin in the sorted order
-    int32_t units;        // units of this bin
-    int32_t unit0;        // first global unit index of this bin
+    int32_t pairs;        // pairs per unit (2 * 64 / lanes)
+    int32_t count;        // pairs in this bin            (device-written)
+    int32_t first;        // first sorted position        (device-written)
+    int32_t units;        // units of this bin            (device-written)
+    int32_t unit0;        // first global unit index      (device-written)
+    int32_t n_min, n_max; // target length range          (device-written)
 };
+
+// Static description of the bins, passed by value to the plan kernels.
+struct BinTable {
+    int32_t n_bins;
+    int32_t m_hi[kMaxBins];    // upper query length of each bin (inclusive)
+    int32_t packed[kMaxBins];  // 1: 16-bit bin, 0: 32-bit bin
+    int32_t lanes[kMaxBins];
+    int32_t cols[kMaxBins];
+};
+
+// Sort keys: bin (3 bits) | chunk count code (5 bits) | target length code
+// (8 bits); pairs are processed in descending key order.
+constexpr int kKeyBits = 16;
+constexpr int kKeys = 1 << kKeyBits;
+// The key histogram is split into kSubHist copies (a block uses copy
+// blockIdx % kSubHist) so that concurrent increments rarely share an
+// address; copies are laid out descending-key-major for one linear scan.
+constexpr int kSubHist = 64;
+constexpr int64_t kHistEntries = (int64_t)kKeys * kSubHist;
+constexpr int kScanBlock = 4096;                        // entries per scan block
+constexpr int kScanBlocks = (int)(kHistEntries / kScanBlock);
 
 struct KParams {
     const uint8_t *q_seqs;
@@ -57,6 +81,20 @@ inline bool scoring_packed_ok(int32_t match, int32_t mismatch) {
 
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,
                         hipStream_t stream);
+hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream);
+bool persistent_lanes_supported(int lanes);
+
+struct PlanBuffers {
+    uint16_t *keys;        // [n_pairs]
+    int32_t *order;        // [n_pairs] pair ids in processing order
+    uint32_t *hist;        // [kHistEntries] counts, then cursors
+    uint32_t *block_sums;  // [kScanBlocks]
+    int32_t *binstat;      // [kMaxBins * 3]: count, n_min, n_max
+};
+
+// Plan: bins, keys, counting sort by key (descending) and the unit table.
+hipError_t launch_plan(const KParams &p, const BinTable &bt, const PlanBuffers &pb,
+                       hipStream_t stream);
 bool plain_variant_exists(int lanes, int cols);
 
 }  // namespace salo

@@ -479,6 +479,49 @@ __global__ __launch_bounds__(64) void plain_kernel(KParams P) {
     }
 }
 
+// Persistent mode: one launch; each wave claims units (a run of
+// near-equal pairs of one length bin, in descending cost order) from an
+// atomic counter until the planned units are exhausted.  The lane-group
+// width comes from the unit's bin; the query columns per lane (K) are fixed
+// per launch so every width shares one register budget.
+template <int K>
+__global__ __launch_bounds__(64) void persistent_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
+    BaseStream qs, ts;
+    qs.init(P.q_seqs, P.q_off, P.n_pairs);
+    ts.init(P.t_seqs, P.t_off, P.n_pairs);
+    uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
+    const int lane = threadIdx.x & (kWave - 1);
+    const int total = __builtin_amdgcn_readfirstlane(*P.total_units);
+    for (;;) {
+        int u = 0;
+        if (lane == 0) u = atomicAdd(P.unit_counter, 1);
+        u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, kWave));
+        if (u >= total) break;
+        int b = 0;
+        for (int k = 0; k < kMaxBins; ++k) {
+            const int u0 = P.bins[k].unit0, nu = P.bins[k].units;
+            if (u >= u0 && u < u0 + nu) b = k;
+        }
+        b = __builtin_amdgcn_readfirstlane(b);
+        const BinDesc &bd = P.bins[b];
+        const int lanes = __builtin_amdgcn_readfirstlane(bd.lanes);
+        const int ppu = __builtin_amdgcn_readfirstlane(bd.pairs);
+        const int64_t first = __builtin_amdgcn_readfirstlane(bd.first);
+        const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
+        const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
+        const int np = (int)min<int64_t>(ppu, first + count - pos0);
+        switch (lanes) {
+            case 2: process_unit<2, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
+            case 4: process_unit<4, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
+            case 8: process_unit<8, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
+            case 16: process_unit<16, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
+            case 32: process_unit<32, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
+            default: process_unit<64, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
+        }
+    }
+}
+
 }  // namespace
 
 #define SALO_PLAIN_VARIANTS(X) \
@@ -502,6 +545,20 @@ hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid, hipStre
     SALO_PLAIN_VARIANTS(X)
 #undef X
     return hipErrorInvalidValue;
+}
+
+bool persistent_lanes_supported(int lanes) {
+    return lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64;
+}
+
+hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream) {
+    if (cols == 16)
+        hipLaunchKernelGGL((persistent_kernel<16>), dim3(grid), dim3(kWave), 0, stream, p);
+    else if (cols == 8)
+        hipLaunchKernelGGL((persistent_kernel<8>), dim3(grid), dim3(kWave), 0, stream, p);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 }  // namespace salo

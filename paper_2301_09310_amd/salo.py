@@ -34,8 +34,8 @@ class Scoring(ctypes.Structure):
 class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("cols", ctypes.c_int32), ("force_int32", ctypes.c_int32),
-                ("waves_per_cu", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 3)]
+                ("waves_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
+                ("reserved", ctypes.c_int32 * 2)]
 
 
 _lock = threading.Lock()
@@ -67,6 +67,9 @@ def load(path: str | None = None):
         lib.salo_last_error.restype = ctypes.c_char_p
         lib.salo_release.argtypes = []
         lib.salo_release.restype = None
+        lib.salo_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float),
+                                         ctypes.POINTER(ctypes.c_float)]
+        lib.salo_last_timing.restype = i32
         lib.salo_version.argtypes = []
         lib.salo_version.restype = i32
         if path is None:
@@ -86,8 +89,10 @@ def _stream_handle(stream):
     return ctypes.c_void_p(stream.cuda_stream)
 
 
-def make_options(mode="auto", lanes=0, cols=0, force_int32=False, waves_per_cu=0):
+def make_options(mode="auto", lanes=0, cols=0, force_int32=False, waves_per_cu=0,
+                 timing=False):
     o = Options()
+    o.timing = 1 if timing else 0
     o.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
     o.lanes, o.cols = int(lanes), int(cols)
     o.force_int32 = 1 if force_int32 else 0
@@ -103,7 +108,7 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
     int64 CUDA tensors of n_pairs+1 entries.  Returns (score, q_end, t_end)
     int32 CUDA tensors (or fills `out`, a triple of such tensors).  Keyword
     options: mode ('auto' | 'plain' | 'persistent'), lanes, cols,
-    force_int32, waves_per_cu.
+    force_int32, waves_per_cu, timing.
     """
     import torch
     lib = load()
@@ -137,6 +142,14 @@ def align_batch_raw(q_ptr, q_off_ptr, t_ptr, t_off_ptr, n_pairs, scoring, s_ptr,
     return lib.salo_align_batch_ex(q_ptr, q_off_ptr, t_ptr, t_off_ptr, int(n_pairs),
                                    Scoring(*[int(x) for x in scoring]), s_ptr, qe_ptr, te_ptr,
                                    stream_handle, ctypes.byref(opts))
+
+
+def last_timing(stream=None):
+    """(plan_ms, dp_ms) of the last call made with timing=True on `stream`."""
+    lib = load()
+    a, b = ctypes.c_float(0), ctypes.c_float(0)
+    _check(lib, lib.salo_last_timing(_stream_handle(stream), ctypes.byref(a), ctypes.byref(b)))
+    return float(a.value), float(b.value)
 
 
 def reserve(max_pairs: int, stream=None):

@@ -29,7 +29,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
-              "salo_error_count", "salo_last_error", "salo_release", "salo_version"]:
+              "salo_error_count", "salo_last_timing", "salo_last_error", "salo_release",
+              "salo_version"]:
         assert n in names
 
 
@@ -82,6 +83,9 @@ def test_misaligned_stream(lib):
 def test_bad_options(lib):
     o = salo.make_options()
     o.reserved[1] = 3
+    assert _call(5, opts=o) == -1
+    o = salo.make_options()
+    o.reserved[0] = 1
     assert _call(5, opts=o) == -1
     o = salo.make_options()
     o.mode = 9

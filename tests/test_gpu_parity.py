@@ -159,3 +159,48 @@ def test_invalid_pairs_are_flagged(dev):
     ok = [p for p in range(40) if p not in (9, 10, 20, 21)]
     for k in range(3):
         assert np.array_equal(got[k][ok], want[k][ok])
+
+
+@pytest.mark.parametrize("lanes", [2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("cols", [8, 16])
+def test_persistent_forced_widths(dev, lanes, cols):
+    b = _edge_batch()
+    want = oracle_align(b)
+    _say("edge cases persistent lanes=%d cols=%d" % (lanes, cols))
+    assert_same(b, gpu_align(b, mode="persistent", lanes=lanes, cols=cols), want,
+                "persistent lanes=%d cols=%d" % (lanes, cols))
+
+
+def test_modes_agree_on_mixed_lengths(dev):
+    """Plain and persistent (binned, sorted) runs give identical outputs."""
+    b = I.random_pairs(31, 3000, 1500, related=0.7)
+    want = oracle_align(b)
+    for mode, kw in [("persistent", {}), ("persistent", {"cols": 8}),
+                     ("plain", {"lanes": 8, "cols": 16}), ("auto", {}),
+                     ("persistent", {"force_int32": True})]:
+        _say("random_pairs seed 31 mode", mode, kw)
+        assert_same(b, gpu_align(b, mode=mode, **kw), want, "mode %s %s" % (mode, kw))
+
+
+def test_short_reads_subset(dev):
+    """200,000 pairs of the short-read workload, every pair checked."""
+    b = I.short_reads(0, 200_000)
+    want = oracle_align(b)
+    _say("short_reads 200k pairs default")
+    assert_same(b, gpu_align(b), want, "short_reads 200k")
+    _say("short_reads 200k pairs plain")
+    assert_same(b, gpu_align(b, mode="plain"), want, "short_reads 200k plain")
+
+
+def test_long_uneven_sample(dev):
+    b = I.long_uneven(0, 2000)
+    want = oracle_align(b)
+    _say("long_uneven 2000 pairs default")
+    assert_same(b, gpu_align(b), want, "long_uneven 2000")
+
+
+def test_mixed_sample(dev):
+    b = I.mixed(0, 6000)
+    want = oracle_align(b)
+    _say("mixed 6000 pairs default")
+    assert_same(b, gpu_align(b), want, "mixed 6000")
