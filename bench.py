@@ -54,6 +54,9 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--parity-sample", type=int, default=3000)
     ap.add_argument("--compare-plain", action="store_true")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
+                    help="only run 3 device-to-device copies of BYTES bytes (a known-"
+                         "traffic kernel for scaling the profiler's byte counters)")
     ap.add_argument("--plain-lanes", type=int, default=4)
     args = ap.parse_args(argv)
 
@@ -73,6 +76,15 @@ def main(argv=None) -> int:
         return 2
     salo.load()
     dev = torch.device("cuda:0")
+
+    if args.calibrate_copy:
+        src = torch.ones(args.calibrate_copy, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        log("copied %d bytes 3 times" % args.calibrate_copy)
+        return 0
 
     gen = I.WORKLOADS[args.workload]
     t0 = time.time()

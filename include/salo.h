@@ -96,6 +96,20 @@ typedef struct {
     int32_t reserved[2];    /* must be 0 */
 } salo_options_t;
 
+/* One length bin of the persistent mode: pairs whose query length is at
+ * most m_hi (and above the previous bin's m_hi of the same kind), with
+ * 16-bit cells (packed = 1) or 32-bit cells (packed = 0), run in lane
+ * groups of `lanes` lanes.  A pair whose target is too long for its bin's
+ * width (more than 1024 * lanes bases) moves to the next bin of its kind. */
+typedef struct {
+    int32_t m_hi;       /* 1..65535, increasing within each kind */
+    int32_t packed;     /* 1: 16-bit bin, 0: 32-bit bin */
+    int32_t lanes;      /* 1, 2, 4, 8, 16, 32 or 64 */
+    int32_t reserved;   /* must be 0 */
+} salo_bin_t;
+
+#define SALO_MAX_BINS 16
+
 /*
  * Align n_pairs pairs (Eq. 1 of Section II-A per pair) with default options.
  * Arguments: packed query stream, its int64 offsets [n_pairs+1], packed
@@ -136,6 +150,18 @@ salo_status_t salo_error_count(hipStream_t stream, int64_t *host_count);
  * on `stream` around those launches.  Synchronises on the events.  Returns
  * SALO_ERR_INVALID when no timed call has run on that stream. */
 salo_status_t salo_last_timing(hipStream_t stream, float *plan_ms, float *dp_ms);
+
+/* Replace the process-wide length-bin table of the persistent mode (the
+ * lane-group width per query-length bin, normally written by the
+ * autotuner).  bins may be NULL with n_bins == 0 to restore the built-in
+ * table.  Each kind (16-bit, 32-bit) needs at least one bin and its last
+ * bin must have m_hi = 65535.  Applies to calls made after it returns;
+ * results never depend on the table. */
+salo_status_t salo_set_bins(const salo_bin_t *bins, int32_t n_bins);
+
+/* Copy the current bin table into bins[0 .. max_bins-1]; *n_bins receives
+ * the table's length. */
+salo_status_t salo_get_bins(salo_bin_t *bins, int32_t max_bins, int32_t *n_bins);
 
 /* Message for the last non-OK status returned on this host thread. */
 const char *salo_last_error(void);

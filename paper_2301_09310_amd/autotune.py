@@ -1,0 +1,134 @@
+"""Autotuner of the persistent mode's lane-group width per length bin.
+
+For every bin of the table (a query-length range, 16-bit or 32-bit cells)
+it draws a synthetic batch whose queries fall in that range (targets 1.0 to
+1.5 times the query, half of the pairs related), times the persistent
+kernel with each admissible width forced, and keeps the fastest.  The
+width is the paper's subwarp-size knob (SALoBa, Section IV-C, and its sweep
+of Section V-D): narrow groups waste less of the wavefront's ramp and of the
+last chunk, wide groups finish a long pair sooner.
+
+Usage (on the GPU):
+  python -m paper_2301_09310_amd.autotune --out paper_2301_09310_amd/tune_gfx950.json
+The JSON holds the table and every measurement; salo.load_tune_table(path)
+installs it, and the library's built-in table is a copy of the last run.
+"""
+from __future__ import annotations
+
+import argparse
+import datetime
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+WIDTHS = (1, 2, 4, 8, 16, 32, 64)
+ROWS_PER_LANE = 1024     # a width-W bin admits targets of up to 1024*W bases
+
+
+def bin_batch(m_lo: int, m_hi: int, cells: float, seed: int, min_pairs: int = 256):
+    """Pairs with queries in (m_lo, m_hi], targets 1.0-1.5x, ~`cells` cells."""
+    from paper_2301_09310_amd import inputs as I
+    rng = np.random.default_rng([seed, m_hi])
+    lo = max(m_lo + 1, 1)
+    hi = min(m_hi, 12000)
+    mean_cells = ((lo + hi) / 2.0) ** 2 * 1.25
+    # enough pairs for the target cell count, and for several units per
+    # resident wave even at the widest width (2 pairs per unit)
+    n = int(max(min_pairs, min(2_000_000, cells / mean_cells)))
+    ql = rng.integers(lo, hi + 1, n)
+    tl = np.minimum(np.rint(ql * rng.uniform(1.0, 1.5, n)).astype(np.int64), 65535)
+    qs, ts = [], []
+    t_all = rng.integers(0, 4, int(tl.sum()), dtype=np.uint8)
+    q_all = rng.integers(0, 4, int(ql.sum()), dtype=np.uint8)
+    to = np.concatenate([[0], np.cumsum(tl)])
+    qo = np.concatenate([[0], np.cumsum(ql)])
+    related = rng.random(n) < 0.5
+    for p in np.nonzero(related)[0]:
+        # copy a window of the target into the query (with no mutations: the
+        # width choice depends on shape, not on the alignment's content)
+        k = int(min(ql[p], tl[p]))
+        q_all[qo[p]:qo[p] + k] = t_all[to[p]:to[p] + k]
+    b = I.Batch(I.pack_bases(q_all), qo.astype(np.int64), I.pack_bases(t_all),
+                to.astype(np.int64))
+    return b
+
+
+def time_config(dev_batch, n, reps=3, **opts):
+    import torch
+    from paper_2301_09310_amd import salo
+    q, qo, t, to = dev_batch
+    out = tuple(torch.empty(n, dtype=torch.int32, device=q.device) for _ in range(3))
+    salo.align_batch(q, qo, t, to, out=out, **opts)
+    torch.cuda.synchronize()
+    ms = []
+    for _ in range(reps):
+        salo.align_batch(q, qo, t, to, out=out, timing=True, **opts)
+        ms.append(sum(salo.last_timing()))
+    return float(np.median(ms)), out
+
+
+def tune(cells_per_bin: float = 2e10, cols: int = 16, seed: int = 7, log=print):
+    import torch
+    from paper_2301_09310_amd import salo
+    cus = torch.cuda.get_device_properties(0).multi_processor_count
+    min_pairs = 4 * cus * 12 * 2      # 4 units per resident wave at 2 pairs/unit
+    salo.set_bins(None)
+    table = salo.get_bins()
+    prev = {0: 0, 1: 0}
+    result = []
+    for m_hi, packed, default_w in table:
+        m_lo = prev[packed]
+        prev[packed] = m_hi
+        b = bin_batch(m_lo, m_hi, cells_per_bin, seed, min_pairs=min_pairs)
+        n_max = int(b.t_lens().max())
+        dev = salo.to_device(b)
+        timings = {}
+        ref = None
+        for w in WIDTHS:
+            if n_max > ROWS_PER_LANE * w:
+                continue
+            ms, out = time_config(dev, b.n_pairs, mode="persistent", lanes=w, cols=cols,
+                                  force_int32=not packed)
+            res = tuple(x.cpu() for x in out)
+            if ref is None:
+                ref = res
+            elif not all(torch.equal(x, y) for x, y in zip(res, ref)):
+                raise RuntimeError("width %d changed the results of bin %d" % (w, m_hi))
+            timings[w] = ms
+        best = min(timings, key=timings.get)
+        gcups = b.cells() / (timings[best] * 1e-3) / 1e9
+        log("bin m<=%5d %s: %d pairs %.2e cells; best lanes %d (%.0f GCUPS); %s" % (
+            m_hi, "16-bit" if packed else "32-bit", b.n_pairs, b.cells(), best, gcups,
+            " ".join("%d:%.2fms" % (w, t) for w, t in timings.items())))
+        result.append({"m_hi": m_hi, "packed": packed, "lanes": best, "pairs": b.n_pairs,
+                       "cells": b.cells(), "ms": {str(w): round(t, 4) for w, t in timings.items()}})
+    return result
+
+
+def main(argv=None) -> int:
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tune_gfx950.json"))
+    ap.add_argument("--cells-per-bin", type=float, default=2e10)
+    ap.add_argument("--cols", type=int, default=16)
+    args = ap.parse_args(argv)
+    import torch
+    from paper_2301_09310_amd import salo
+    salo.load()
+    t0 = time.time()
+    bins = tune(args.cells_per_bin, args.cols, log=lambda *a: print(*a, flush=True))
+    props = torch.cuda.get_device_properties(0)
+    rec = {"arch": getattr(props, "gcnArchName", "gfx950"), "device": props.name,
+           "cus": props.multi_processor_count, "cols": args.cols,
+           "date": datetime.date.today().isoformat(), "seconds": round(time.time() - t0, 1),
+           "bins": bins}
+    with open(args.out, "w") as f:
+        json.dump(rec, f, indent=1)
+    print("wrote", args.out, flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -3,6 +3,8 @@
 // alignment itself runs in the gfx950 kernels (salo_kernels.hip).
 #include <mutex>
 #include <map>
+#include <vector>
+#include <iterator>
 #include <string>
 #include <utility>
 #include <cstdio>
@@ -129,22 +131,38 @@ salo_status_t ensure_plan(Workspace &ws, int64_t n_pairs, hipStream_t stream) {
     return SALO_OK;
 }
 
-// Default length bins (query length upper bounds) and lane-group widths.
-// 16-bit bins first, then 32-bit bins; K = 16 query columns per lane.
-BinTable default_bins(int cols, int forced_lanes) {
+// Length bins of the persistent mode: (m_hi, packed, lanes).  Query-length
+// ranges double from bin to bin; the built-in widths come from the
+// autotuner's sweep on one MI355X and can be replaced with salo_set_bins.
+const salo_bin_t kDefaultBins[] = {
+    {64, 1, 1, 0},   {128, 1, 2, 0},  {256, 1, 2, 0},   {512, 1, 4, 0},
+    {1024, 1, 8, 0}, {2048, 1, 16, 0}, {4096, 1, 32, 0}, {65535, 1, 64, 0},
+    {1024, 0, 4, 0}, {65535, 0, 16, 0},
+};
+
+std::mutex g_bins_mu;
+std::vector<salo_bin_t> g_bins(std::begin(kDefaultBins), std::end(kDefaultBins));
+
+BinTable make_bin_table(int cols, int forced_lanes) {
+    std::lock_guard<std::mutex> lk(g_bins_mu);
     BinTable bt;
     std::memset(&bt, 0, sizeof bt);
-    const int32_t m_hi[] = {96, 200, 400, 1000, 3000, 65535, 1000, 65535};
-    const int32_t packed[] = {1, 1, 1, 1, 1, 1, 0, 0};
-    const int32_t lanes[] = {2, 2, 4, 8, 16, 32, 4, 16};
-    bt.n_bins = 8;
-    for (int b = 0; b < 8; ++b) {
-        bt.m_hi[b] = m_hi[b];
-        bt.packed[b] = packed[b];
-        bt.lanes[b] = forced_lanes ? forced_lanes : lanes[b];
+    bt.n_bins = (int32_t)g_bins.size();
+    int32_t prev_hi[2] = {0, 0};
+    for (int b = 0; b < bt.n_bins; ++b) {
+        const salo_bin_t &e = g_bins[b];
+        bt.m_lo[b] = prev_hi[e.packed];
+        bt.m_hi[b] = e.m_hi;
+        prev_hi[e.packed] = e.m_hi;
+        bt.packed[b] = e.packed;
+        bt.lanes[b] = forced_lanes ? forced_lanes : e.lanes;
         bt.cols[b] = cols;
     }
     return bt;
+}
+
+bool lanes_ok(int32_t w) {
+    return w == 1 || w == 2 || w == 4 || w == 8 || w == 16 || w == 32 || w == 64;
 }
 
 salo_status_t validate(const uint8_t *q_seqs, const int64_t *q_offsets, const uint8_t *t_seqs,
@@ -202,7 +220,10 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
     st = get_workspace(stream, &ws);
     if (st != SALO_OK) return st;
 
-    const int wpc = o.waves_per_cu ? o.waves_per_cu : 8;
+    // resident waves per CU at the kernel's register budget: 3 per SIMD for
+    // 8 or 16 query columns per lane, 2 per SIMD for 32
+    const int cols_req = o.cols ? o.cols : 16;
+    const int wpc = o.waves_per_cu ? o.waves_per_cu : (cols_req >= 32 ? 8 : 12);
     const int64_t grid = (int64_t)ws->cus * wpc;
     st = ensure_slots(*ws, grid, stream);
     if (st != SALO_OK) return st;
@@ -253,13 +274,13 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
 
     // persistent, length-binned
     const int cols = o.cols ? o.cols : 16;
-    if (cols != 8 && cols != 16)
-        return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports cols 8 or 16");
+    if (cols != 8 && cols != 16 && cols != 32)
+        return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports cols 8, 16 or 32");
     if (o.lanes && !persistent_lanes_supported(o.lanes))
         return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports lanes 2..64");
     st = ensure_plan(*ws, n_pairs, stream);
     if (st != SALO_OK) return st;
-    const BinTable bt = default_bins(cols, o.lanes);
+    const BinTable bt = make_bin_table(cols, o.lanes);
     p.n_bins = bt.n_bins;
     PlanBuffers pb{ws->keys, ws->order, ws->hist, ws->block_sums, ws->binstat};
     hipError_t e = launch_plan(p, bt, pb, stream);
@@ -284,7 +305,7 @@ salo_status_t salo_reserve(int64_t max_pairs, hipStream_t stream) {
     Workspace *ws = nullptr;
     salo_status_t st = get_workspace(stream, &ws);
     if (st != SALO_OK) return st;
-    st = ensure_slots(*ws, (int64_t)ws->cus * 8, stream);
+    st = ensure_slots(*ws, (int64_t)ws->cus * 12, stream);
     if (st != SALO_OK) return st;
     return ensure_plan(*ws, max_pairs, stream);
 }
@@ -321,6 +342,43 @@ salo_status_t salo_last_timing(hipStream_t stream, float *plan_ms, float *dp_ms)
         return hip_fail(e, "hipEventElapsedTime");
     *plan_ms = ws->timed_plan ? a : 0.f;
     *dp_ms = b;
+    return SALO_OK;
+}
+
+salo_status_t salo_set_bins(const salo_bin_t *bins, int32_t n_bins) {
+    if (n_bins == 0 && bins == nullptr) {
+        std::lock_guard<std::mutex> lk(g_bins_mu);
+        g_bins.assign(std::begin(kDefaultBins), std::end(kDefaultBins));
+        return SALO_OK;
+    }
+    if (!bins || n_bins < 2 || n_bins > kMaxBins)
+        return fail(SALO_ERR_INVALID, "need 2..16 bins");
+    int32_t prev[2] = {0, 0};
+    bool last_full[2] = {false, false};
+    int have[2] = {0, 0};
+    for (int b = 0; b < n_bins; ++b) {
+        const salo_bin_t &e = bins[b];
+        if ((e.packed != 0 && e.packed != 1) || e.reserved != 0 || !lanes_ok(e.lanes))
+            return fail(SALO_ERR_INVALID, "bin " + std::to_string(b) + ": bad packed/lanes");
+        if (e.m_hi <= prev[e.packed] || e.m_hi > SALO_MAX_LEN)
+            return fail(SALO_ERR_INVALID, "bin " + std::to_string(b) +
+                                              ": m_hi must increase within its kind");
+        prev[e.packed] = e.m_hi;
+        last_full[e.packed] = e.m_hi == SALO_MAX_LEN;
+        have[e.packed]++;
+    }
+    if (!have[0] || !have[1] || !last_full[0] || !last_full[1])
+        return fail(SALO_ERR_INVALID, "each kind needs bins ending at m_hi = 65535");
+    std::lock_guard<std::mutex> lk(g_bins_mu);
+    g_bins.assign(bins, bins + n_bins);
+    return SALO_OK;
+}
+
+salo_status_t salo_get_bins(salo_bin_t *bins, int32_t max_bins, int32_t *n_bins) {
+    if (!n_bins || (max_bins > 0 && !bins)) return fail(SALO_ERR_INVALID, "NULL pointer");
+    std::lock_guard<std::mutex> lk(g_bins_mu);
+    *n_bins = (int32_t)g_bins.size();
+    for (int b = 0; b < max_bins && b < (int)g_bins.size(); ++b) bins[b] = g_bins[b];
     return SALO_OK;
 }
 

@@ -14,7 +14,7 @@ constexpr int64_t kSlotWords = kSlotBytes / 4;
 
 // Length bins of the persistent mode (by query length, and by target
 // length so that every bin's boundary column fits a slot).
-constexpr int kMaxBins = 8;
+constexpr int kMaxBins = 16;
 constexpr int64_t SALO_MAX_LEN_DEV = 65535;
 
 // One length bin: the pairs whose query length falls in (m_lo, m_hi] and
@@ -34,14 +34,16 @@ struct BinDesc {
 // Static description of the bins, passed by value to the plan kernels.
 struct BinTable {
     int32_t n_bins;
+    int32_t m_lo[kMaxBins];    // lower query length of each bin (exclusive)
     int32_t m_hi[kMaxBins];    // upper query length of each bin (inclusive)
     int32_t packed[kMaxBins];  // 1: 16-bit bin, 0: 32-bit bin
     int32_t lanes[kMaxBins];
     int32_t cols[kMaxBins];
 };
 
-// Sort keys: bin (3 bits) | chunk count code (5 bits) | target length code
-// (8 bits); pairs are processed in descending key order.
+// Sort keys: bin (4 bits) | chunk count above the bin's minimum (4 bits,
+// capped) | target length code (8 bits); pairs are processed in descending
+// key order.
 constexpr int kKeyBits = 16;
 constexpr int kKeys = 1 << kKeyBits;
 // The key histogram is split into kSubHist copies (a block uses copy

@@ -65,44 +65,59 @@ constexpr int32_t kBufDword3 = 0x00020000;   // raw buffer descriptor, gfx9 fami
 // A packed base stream behind a range-checked buffer descriptor: reads
 // outside [0, nbytes) return 0 instead of touching memory.
 struct BaseStream {
-    __amdgpu_buffer_rsrc_t rsrc;
+    const uint8_t *base;   // wave-uniform
+    int32_t nbytes;        // wave-uniform, whole 32-bit words
 
-    __device__ void init(const uint8_t *p, const int64_t *off, int64_t n_pairs) {
+    __device__ __forceinline__ void init(const uint8_t *p, const int64_t *off, int64_t n_pairs) {
         int64_t bases = n_pairs > 0 ? off[n_pairs] : 0;
-        int64_t bytes = ((bases + 15) >> 4) << 2;          // whole 32-bit words
+        int64_t bytes = ((bases + 15) >> 4) << 2;
         if (bytes < 0) bytes = 0;
         if (bytes > 0xFFFFFFF0ll) bytes = 0xFFFFFFF0ll;
-        rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<uint8_t *>(p), 0,
-                                                 (int)(uint32_t)bytes, kBufDword3);
+        base = p;
+        nbytes = __builtin_amdgcn_readfirstlane((int)(uint32_t)bytes);
     }
     __device__ __forceinline__ uint32_t word(int64_t w) const {
+        // the descriptor is rebuilt from scalar values at every use so that
+        // it stays in SGPRs (no waterfall loop)
+        const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+            const_cast<uint8_t *>(base), 0, nbytes, kBufDword3);
         const uint32_t off = (w < 0 || w >= (int64_t(1) << 30)) ? 0xFFFFFFF0u
                                                                 : (uint32_t)w << 2;
         return (uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rsrc, (int)off, 0, 0);
     }
 };
 
-// DPP moves of the value `v` from lane-1 to lane, with `bnd` at each
-// group's first lane.
-template <int W>
-__device__ __forceinline__ uint32_t shift_in(uint32_t v, uint32_t bnd, int l) {
-    if constexpr (W == 1) {
-        return bnd;
-    } else if constexpr (W == 16) {
-        // row_shr:1 -- lanes 0/16/32/48 have no source and keep `bnd`
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x111, 0xf, 0xf, false);
-    } else if constexpr (W == 64) {
-        // wave_shr:1 -- lane 0 keeps `bnd`
-        return (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x138, 0xf, 0xf, false);
-    } else if constexpr (W < 16) {
-        const uint32_t s =
-            (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x111, 0xf, 0xf, false);
-        return l == 0 ? bnd : s;
-    } else {  // W == 32
-        const uint32_t s =
-            (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x138, 0xf, 0xf, false);
-        return l == 0 ? bnd : s;
+typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+
+// The wave's boundary-column slot behind a range-checked buffer descriptor:
+// an index outside the slot reads 0 and drops the store.
+struct Slot {
+    uint32_t *base;   // wave-uniform
+
+    __device__ __forceinline__ uint2 load(size_t entry) const {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)kSlotBytes, kBufDword3);
+        const uint32_t off = entry < (size_t)(kSlotWords / 2) ? (uint32_t)entry * 8u : 0xFFFFFFF0u;
+        const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
+        return make_uint2(v.x, v.y);
     }
+    __device__ __forceinline__ void store(size_t entry, uint32_t h, uint32_t e) const {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)kSlotBytes, kBufDword3);
+        const uint32_t off = entry < (size_t)(kSlotWords / 2) ? (uint32_t)entry * 8u : 0xFFFFFFF0u;
+        u32x2 v;
+        v.x = h;
+        v.y = e;
+        __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
+    }
+};
+
+// DPP move of `v` from lane-1 to every lane (wave_shr:1), with `bnd` at
+// each group's first lane (l == 0), whatever the group width.
+__device__ __forceinline__ uint32_t shift_in(uint32_t v, uint32_t bnd, int l) {
+    const uint32_t s =
+        (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x138, 0xf, 0xf, false);
+    return l == 0 ? bnd : s;
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -128,10 +143,14 @@ struct PairRef {
     bool invalid;
 };
 
-__device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, bool present) {
+// The pair at position `pos` of the processing order, or an absent pair
+// (no output, m = n = 0) when pos is outside [0, pos_end).
+__device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, int64_t pos_end,
+                                             bool present) {
     PairRef r{0, 0, 0, 0, -1, false};
-    if (!present || pos >= P.n_pairs) return r;
+    if (!present || pos < 0 || pos >= pos_end || pos >= P.n_pairs) return r;
     const int64_t p = P.order ? (int64_t)P.order[pos] : pos;
+    if (p < 0 || p >= P.n_pairs) return r;     // never for a consistent plan
     const int64_t q0 = P.q_off[p], q1 = P.q_off[p + 1];
     const int64_t t0 = P.t_off[p], t1 = P.t_off[p + 1];
     r.id = (int32_t)p;
@@ -146,12 +165,12 @@ __device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, bool
 
 struct Best {
     int32_t score, row, col;
-    __device__ void offer(int32_t s, int32_t r, int32_t c) {
+    __device__ __forceinline__ void offer(int32_t s, int32_t r, int32_t c) {
         if (s > score || (s == score && s > 0 && (r < row || (r == row && c < col)))) {
             score = s; row = r; col = c;
         }
     }
-    __device__ uint64_t key() const {
+    __device__ __forceinline__ uint64_t key() const {
         if (score <= 0) return 0;
         return ((uint64_t)(uint32_t)score << 32) | ((uint64_t)(0xFFFFu - (uint32_t)row) << 16) |
                (uint64_t)(0xFFFFu - (uint32_t)col);
@@ -173,22 +192,24 @@ __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr
 
 // One unit: G = 64/W groups; each group aligns NPG pairs (2 packed, 1 wide).
 // pos0: first position (in processing order) of the unit's pairs.
-// gsel: -1 = all groups, else only group gsel is processed (used when the
-// unit's boundary columns do not fit a slot together).
-template <int W, int K, bool PK>
-__device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs, const BaseStream &ts,
-                         int64_t pos0, int gsel, uint32_t *slot, uint32_t *lds_saved) {
-    constexpr int G = kWave / W;
+// [g0, g0 + gn): the groups processed in this pass (all G normally; fewer
+// when the unit's boundary columns do not fit one slot together).
+template <int K, bool PK>
+__device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
+                         int64_t pos0, int64_t pos_end, int g0, int gn, int W,
+                         uint32_t *slot, uint32_t *lds_saved) {
+    const int G = kWave / W;
     constexpr int NPG = PK ? 2 : 1;
-    static_assert(K % 4 == 0 && K <= 16, "K must be 4..16, multiple of 4");
+    static_assert(K % 4 == 0 && K <= 32, "K must be 4..32, multiple of 4");
     const int lane = threadIdx.x & (kWave - 1);
-    const int g = lane / W;
-    const int l = lane % W;
-    const bool mine = gsel < 0 || g == gsel;
+    const int g = lane / W;          // W is a power of two
+    const int l = lane & (W - 1);
+    const bool mine = g >= g0 && g < g0 + gn;
 
     PairRef pr[NPG];
 #pragma unroll
-    for (int h = 0; h < NPG; ++h) pr[h] = load_pair(P, pos0 + (int64_t)g * NPG + h, mine);
+    for (int h = 0; h < NPG; ++h)
+        pr[h] = load_pair(P, pos0 + (int64_t)g * NPG + h, pos_end, mine);
 
     int rmax = 0, mmax = 0;
 #pragma unroll
@@ -200,8 +221,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
     // no target rows: every score is 0 and no boundary row may be touched
     const int Cw = wave_max((mmax + W * K - 1) / (W * K));
     const int C = R > 0 ? Cw : 0;
-    const int Gs = gsel < 0 ? G : 1;
-    const int gs = gsel < 0 ? g : 0;
+    const int Gs = gn;           // groups sharing the slot, row-interleaved
+    // slot column of this lane's group; lanes of groups outside this pass
+    // still issue the (unused) boundary prefetch, so they read column 0
+    const int gs = mine ? g - g0 : 0;
 
     Best best[NPG];
 #pragma unroll
@@ -226,36 +249,50 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
     }
 
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
+    const Slot bslot{slot};
 
     for (int c = 0; c < C; ++c) {
         const int col0 = c * W * K + l * K;
         // query selectors (PK) or query bases (wide) of this lane's K columns
         uint32_t SEL[K];
         {
-            uint32_t qw[NPG];
+            // this lane's query bases as up to two 16-base words per pair
+            constexpr int NQW = (K + 15) / 16;
+            uint32_t qw[NPG][NQW];
 #pragma unroll
             for (int h = 0; h < NPG; ++h) {
                 const int64_t p0 = pr[h].q0 + col0;
-                const uint32_t lo = qs.word(p0 >> 4), hi = qs.word((p0 >> 4) + 1);
-                qw[h] = __builtin_amdgcn_alignbit(hi, lo, (uint32_t)(p0 & 15) * 2u);
+                const uint32_t sh = (uint32_t)(p0 & 15) * 2u;
+                uint32_t prev = qs.word(p0 >> 4);
+#pragma unroll
+                for (int w = 0; w < NQW; ++w) {
+                    const uint32_t next = qs.word((p0 >> 4) + 1 + w);
+                    qw[h][w] = __builtin_amdgcn_alignbit(next, prev, sh);
+                    prev = next;
+                }
             }
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if constexpr (PK) {
-                    const uint32_t sA = (col0 + k < pr[0].m) ? ((qw[0] >> (2 * k)) & 3u) : 12u;
-                    const uint32_t sB = (col0 + k < pr[1].m) ? (4u + ((qw[1] >> (2 * k)) & 3u)) : 12u;
+                    const uint32_t sA = (col0 + k < pr[0].m)
+                                            ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u) : 12u;
+                    const uint32_t sB = (col0 + k < pr[1].m)
+                                            ? (4u + ((qw[1][k >> 4] >> (2 * (k & 15))) & 3u)) : 12u;
                     SEL[k] = sA | (sB << 16) | 0x0C000C00u;
                 } else {
-                    SEL[k] = (col0 + k < pr[0].m) ? ((qw[0] >> (2 * k)) & 3u) : 5u;
+                    SEL[k] = (col0 + k < pr[0].m) ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u)
+                                                  : 5u;
                 }
             }
         }
 
-        uint32_t H[K], HA[K], F[K];
+        // per column: H of the last row (the next row's diagonal) and F of
+        // the next row, F(i+1,j) = max(F(i,j) - beta, H(i,j) - alpha)
+        uint32_t H[K], F[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            H[k] = 0; F[k] = 0;
-            HA[k] = PK ? 0u : (uint32_t)(-alpha);
+            H[k] = 0;
+            F[k] = 0;
         }
         uint32_t hprev = 0;           // H(i-1, col0-1)
         uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
@@ -272,7 +309,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
             fifo[r] = make_uint2(0u, 0u);
             if (have_bnd) {
                 const int rr = min(r, R - 1);
-                fifo[r] = *reinterpret_cast<const uint2 *>(slot + 2 * ((size_t)rr * Gs + gs));
+                fifo[r] = bslot.load((size_t)rr * Gs + gs);
             }
         }
 
@@ -307,10 +344,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
                 const uint2 bnd = fifo[j & 3];
                 if (have_bnd) {
                     const int rr = min(s + 4, R - 1);
-                    fifo[j & 3] = *reinterpret_cast<const uint2 *>(slot + 2 * ((size_t)rr * Gs + gs));
+                    fifo[j & 3] = bslot.load((size_t)rr * Gs + gs);
                 }
-                const uint32_t hin = shift_in<W>(hout, bnd.x, l);
-                const uint32_t ein = shift_in<W>(eout, bnd.y, l);
+                const uint32_t hin = shift_in(hout, bnd.x, l);
+                const uint32_t ein = shift_in(eout, bnd.y, l);
                 if (i >= 0 && i < R) {
                     uint32_t e = ein;
                     uint32_t hd = hprev;
@@ -325,12 +362,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
                             const uint32_t T = __builtin_amdgcn_perm(TB, TA, SEL[k]);
                             const uint32_t d = psub(padd(hd, T), NB2);
                             hd = H[k];
-                            const uint32_t f = pmax(psub(F[k], BE2), HA[k]);
-                            F[k] = f;
+                            const uint32_t f = F[k];
                             const uint32_t hh = pmax(pmax(d, f), e);
                             H[k] = hh;
                             const uint32_t ha = psub(hh, AL2);
-                            HA[k] = ha;
+                            F[k] = pmax(psub(f, BE2), ha);
                             rowmax = k == 0 ? hh : pmax(rowmax, hh);
                             e = pmax(psub(e, BE2), ha);
                         }
@@ -341,12 +377,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
                             const int sc = SEL[k] == tb ? a : b;
                             const int d = (int)hd + sc;
                             hd = H[k];
-                            const int f = max3i((int)F[k] - beta, (int)HA[k], 0);
-                            F[k] = (uint32_t)f;
+                            const int f = (int)F[k];
                             const int hh = max3i(d, f, (int)e);
                             H[k] = (uint32_t)hh;
                             const int ha = hh - alpha;
-                            HA[k] = (uint32_t)ha;
+                            F[k] = (uint32_t)max3i(f - beta, ha, 0);
                             rowmax = k == 0 ? (uint32_t)hh : (uint32_t)max((int)rowmax, hh);
                             e = (uint32_t)max3i((int)e - beta, ha, 0);
                         }
@@ -384,8 +419,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
                         }
                     }
                     if (write_bnd && l == W - 1 && mine)
-                        *reinterpret_cast<uint2 *>(slot + 2 * ((size_t)i * Gs + gs)) =
-                            make_uint2(hout, eout);
+                        bslot.store((size_t)i * Gs + gs, hout, eout);
                 }
                 }  // s < S
             }
@@ -420,13 +454,12 @@ __device__ __forceinline__ void run_unit(const KParams &P, const BaseStream &qs,
 }
 
 // A unit is packed-eligible when every pair's score bound stays below 2^15.
-template <int W>
-__device__ bool unit_packed_ok(const KParams &P, int64_t pos0, int npairs) {
+__device__ __forceinline__ bool unit_packed_ok(const KParams &P, int64_t pos0, int npairs) {
     if (!P.packed_ok || P.force_int32) return false;
     const int lane = threadIdx.x & (kWave - 1);
     bool ok = true;
     for (int k = lane; k < npairs; k += kWave) {
-        const PairRef r = load_pair(P, pos0 + k, true);
+        const PairRef r = load_pair(P, pos0 + k, pos0 + npairs, true);
         if (r.id >= 0 && !r.invalid) {
             const int64_t mn = min(r.m, r.n);
             if ((int64_t)P.match * (mn + 1) - (int64_t)P.mismatch > 32767) ok = false;
@@ -435,47 +468,52 @@ __device__ bool unit_packed_ok(const KParams &P, int64_t pos0, int npairs) {
     return __builtin_amdgcn_readfirstlane(__ballot(!ok) == 0ull ? 1 : 0) != 0;
 }
 
-template <int W, int K>
-__device__ void process_unit(const KParams &P, const BaseStream &qs, const BaseStream &ts,
-                             int64_t pos0, int npairs, uint32_t *slot, uint32_t *lds) {
-    constexpr int G = kWave / W;
+template <int K>
+__device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, BaseStream ts,
+                                             int64_t pos0, int npairs, int W, uint32_t *slot,
+                                             uint32_t *lds) {
+    const int G = kWave / W;
     // rows one slot holds for G groups; larger units run one group at a time
     int rmax = 0;
     const int lane = threadIdx.x & (kWave - 1);
     for (int k = lane; k < npairs; k += kWave) {
-        const PairRef r = load_pair(P, pos0 + k, true);
+        const PairRef r = load_pair(P, pos0 + k, pos0 + npairs, true);
         rmax = max(rmax, r.n);
     }
     const int R = wave_max(rmax);
-    // one call site per instantiation keeps run_unit inlined
-    const bool fits = (int64_t)R * G * 2 <= kSlotWords;
-    const int nsel = fits ? 1 : G;
-    if (unit_packed_ok<W>(P, pos0, npairs)) {
-        for (int gp = 0; gp < nsel; ++gp)
-            run_unit<W, K, true>(P, qs, ts, pos0, fits ? -1 : gp, slot, lds);
+    // groups whose boundary columns fit one slot together; a larger unit is
+    // processed in several passes of that many groups.  One call site per
+    // instantiation keeps run_unit inlined.
+    const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(R, 1)));
+    const int passes = (G + fit - 1) / fit;
+    if (unit_packed_ok(P, pos0, npairs)) {
+        for (int ps = 0; ps < passes; ++ps)
+            run_unit<K, true>(P, qs, ts, pos0, pos0 + npairs, ps * fit, min(fit, G - ps * fit),
+                              W, slot, lds);
     } else {
-        for (int it = 0; it < 2 * nsel; ++it) {
-            const int half = it / nsel, gp = it % nsel;
-            run_unit<W, K, false>(P, qs, ts, pos0 + (int64_t)half * G, fits ? -1 : gp, slot, lds);
+        for (int it = 0; it < 2 * passes; ++it) {
+            const int half = it / passes, ps = it % passes;
+            run_unit<K, false>(P, qs, ts, pos0 + (int64_t)half * G, pos0 + npairs, ps * fit,
+                               min(fit, G - ps * fit), W, slot, lds);
         }
     }
 }
 
 // Plain mode: pairs in input order, fixed lanes/cols, units of 128/W pairs
 // dealt to waves round robin.
-template <int W, int K>
-__global__ __launch_bounds__(64) void plain_kernel(KParams P) {
+template <int K>
+__global__ __launch_bounds__(64) void plain_kernel(KParams P, int W) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
     BaseStream qs, ts;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
     ts.init(P.t_seqs, P.t_off, P.n_pairs);
-    constexpr int PPU = 2 * (kWave / W);
-    const int64_t n_units = (P.n_pairs + PPU - 1) / PPU;
+    const int ppu = 2 * (kWave / W);
+    const int64_t n_units = (P.n_pairs + ppu - 1) / ppu;
     uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
-        const int64_t pos0 = u * PPU;
-        const int np = (int)min<int64_t>(PPU, P.n_pairs - pos0);
-        process_unit<W, K>(P, qs, ts, pos0, np, slot, lds_saved);
+        const int64_t pos0 = u * ppu;
+        const int np = (int)min<int64_t>(ppu, P.n_pairs - pos0);
+        process_unit<K>(P, qs, ts, pos0, np, W, slot, lds_saved);
     }
 }
 
@@ -511,48 +549,39 @@ __global__ __launch_bounds__(64) void persistent_kernel(KParams P) {
         const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
         const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
-        switch (lanes) {
-            case 2: process_unit<2, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
-            case 4: process_unit<4, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
-            case 8: process_unit<8, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
-            case 16: process_unit<16, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
-            case 32: process_unit<32, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
-            default: process_unit<64, K>(P, qs, ts, pos0, np, slot, lds_saved); break;
-        }
+        process_unit<K>(P, qs, ts, pos0, np, lanes, slot, lds_saved);
     }
 }
 
 }  // namespace
 
-#define SALO_PLAIN_VARIANTS(X) \
-    X(1, 16) X(2, 16) X(4, 16) X(8, 16) X(16, 16) X(32, 16) X(64, 16) \
-    X(2, 8) X(4, 8) X(8, 8) X(16, 8)
-
 bool plain_variant_exists(int lanes, int cols) {
-#define X(w, k) if (lanes == w && cols == k) return true;
-    SALO_PLAIN_VARIANTS(X)
-#undef X
-    return false;
+    const bool w = lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16 ||
+                   lanes == 32 || lanes == 64;
+    return w && (cols == 8 || cols == 16 || cols == 32);
 }
 
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid, hipStream_t stream) {
-#define X(w, k)                                                                 \
-    if (lanes == w && cols == k) {                                              \
-        hipLaunchKernelGGL((plain_kernel<w, k>), dim3(grid), dim3(kWave), 0,    \
-                           stream, p);                                          \
-        return hipGetLastError();                                               \
-    }
-    SALO_PLAIN_VARIANTS(X)
-#undef X
-    return hipErrorInvalidValue;
+    if (cols == 32)
+        hipLaunchKernelGGL((plain_kernel<32>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
+    else if (cols == 16)
+        hipLaunchKernelGGL((plain_kernel<16>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
+    else if (cols == 8)
+        hipLaunchKernelGGL((plain_kernel<8>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
+    else
+        return hipErrorInvalidValue;
+    return hipGetLastError();
 }
 
 bool persistent_lanes_supported(int lanes) {
-    return lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 || lanes == 64;
+    return lanes == 1 || lanes == 2 || lanes == 4 || lanes == 8 || lanes == 16 || lanes == 32 ||
+           lanes == 64;
 }
 
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream) {
-    if (cols == 16)
+    if (cols == 32)
+        hipLaunchKernelGGL((persistent_kernel<32>), dim3(grid), dim3(kWave), 0, stream, p);
+    else if (cols == 16)
         hipLaunchKernelGGL((persistent_kernel<16>), dim3(grid), dim3(kWave), 0, stream, p);
     else if (cols == 8)
         hipLaunchKernelGGL((persistent_kernel<8>), dim3(grid), dim3(kWave), 0, stream, p);

@@ -13,7 +13,7 @@
 //   plan_zero        clear the histograms and the per-bin statistics
 //   plan_bins        per pair: bin; per bin: count and target length range
 //                    (reduced per block in LDS before one global update)
-//   plan_keys        per pair: 16-bit key = bin | chunk count | length code,
+//   plan_keys        per pair: 16-bit key = bin | relative chunk count | length code,
 //                    counted in sub-histogram blockIdx % kSubHist
 //   plan_scan_*      exclusive scan of all sub-histograms in descending key
 //                    order (block sums, their scan, then the cursors) and
@@ -48,6 +48,9 @@ __device__ __forceinline__ bool pair_packed(const KParams &P, int64_t m, int64_t
     return (int64_t)P.match * (mn + 1) - (int64_t)P.mismatch <= 32767;
 }
 
+// First bin of the pair's kind (16- or 32-bit) whose query range holds m
+// and whose lane-group width keeps the boundary columns of a whole unit in
+// one slot (n rows x 64/W groups x 2 words); else the last bin of the kind.
 __device__ __forceinline__ int pair_bin(const KParams &P, const BinTable &bt, int64_t m,
                                         int64_t n) {
     const int want = pair_packed(P, m, n) ? 1 : 0;
@@ -55,7 +58,8 @@ __device__ __forceinline__ int pair_bin(const KParams &P, const BinTable &bt, in
     for (int b = 0; b < bt.n_bins; ++b) {
         if (bt.packed[b] != want) continue;
         last = b;
-        if (m <= bt.m_hi[b]) return b;
+        const int64_t row_cap = kSlotWords * (int64_t)bt.lanes[b] / (2 * 64);
+        if (m <= bt.m_hi[b] && n <= row_cap) return b;
     }
     return last;
 }
@@ -111,13 +115,14 @@ __global__ __launch_bounds__(kTpb) void plan_keys(KParams P, BinTable bt, PlanBu
     const PairLen L = pair_len(P, p);
     const int b = pair_bin(P, bt, L.m, L.n);
     const int64_t width = (int64_t)bt.lanes[b] * bt.cols[b];
-    int64_t c = (L.m + width - 1) / width;
-    if (c > 31) c = 31;
+    const int64_t c_min = (bt.m_lo[b] + width) / width;   // chunks of the bin's shortest query
+    int64_t c = (L.m + width - 1) / width - c_min;
+    c = c < 0 ? 0 : (c > 15 ? 15 : c);
     const int32_t nmin = pb.binstat[3 * b + 1], nmax = pb.binstat[3 * b + 2];
     const int64_t span = (int64_t)nmax - nmin + 1;
     int64_t nc = span > 0 ? ((L.n - nmin) * 256) / span : 0;
     nc = nc < 0 ? 0 : (nc > 255 ? 255 : nc);
-    const uint32_t key = ((uint32_t)b << 13) | ((uint32_t)c << 8) | (uint32_t)nc;
+    const uint32_t key = ((uint32_t)b << 12) | ((uint32_t)c << 8) | (uint32_t)nc;
     pb.keys[p] = (uint16_t)key;
     atomicAdd(&pb.hist[hist_index(key, blockIdx.x % kSubHist)], 1u);
 }
@@ -209,7 +214,7 @@ __global__ __launch_bounds__(kTpb) void plan_scatter(KParams P, PlanBuffers pb) 
     const int64_t p = (int64_t)blockIdx.x * kTpb + threadIdx.x;
     if (p >= P.n_pairs) return;
     const uint32_t pos = atomicAdd(&pb.hist[hist_index(pb.keys[p], blockIdx.x % kSubHist)], 1u);
-    pb.order[pos] = (int32_t)p;
+    if (pos < (uint64_t)P.n_pairs) pb.order[pos] = (int32_t)p;   // always, for consistent counts
 }
 
 }  // namespace

@@ -38,6 +38,11 @@ class Options(ctypes.Structure):
                 ("reserved", ctypes.c_int32 * 2)]
 
 
+class Bin(ctypes.Structure):
+    _fields_ = [("m_hi", ctypes.c_int32), ("packed", ctypes.c_int32),
+                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
 _lock = threading.Lock()
 _lib = None
 
@@ -70,6 +75,10 @@ def load(path: str | None = None):
         lib.salo_last_timing.argtypes = [vp, ctypes.POINTER(ctypes.c_float),
                                          ctypes.POINTER(ctypes.c_float)]
         lib.salo_last_timing.restype = i32
+        lib.salo_set_bins.argtypes = [ctypes.POINTER(Bin), i32]
+        lib.salo_set_bins.restype = i32
+        lib.salo_get_bins.argtypes = [ctypes.POINTER(Bin), i32, ctypes.POINTER(i32)]
+        lib.salo_get_bins.restype = i32
         lib.salo_version.argtypes = []
         lib.salo_version.restype = i32
         if path is None:
@@ -150,6 +159,33 @@ def last_timing(stream=None):
     a, b = ctypes.c_float(0), ctypes.c_float(0)
     _check(lib, lib.salo_last_timing(_stream_handle(stream), ctypes.byref(a), ctypes.byref(b)))
     return float(a.value), float(b.value)
+
+
+def set_bins(bins):
+    """Install a bin table: a list of (m_hi, packed, lanes); None restores
+    the built-in table."""
+    lib = load()
+    if bins is None:
+        _check(lib, lib.salo_set_bins(None, 0))
+        return
+    arr = (Bin * len(bins))(*[Bin(int(m), int(p), int(w), 0) for m, p, w in bins])
+    _check(lib, lib.salo_set_bins(arr, len(bins)))
+
+
+def get_bins():
+    lib = load()
+    arr = (Bin * 16)()
+    n = ctypes.c_int32(0)
+    _check(lib, lib.salo_get_bins(arr, 16, ctypes.byref(n)))
+    return [(arr[i].m_hi, arr[i].packed, arr[i].lanes) for i in range(n.value)]
+
+
+def load_tune_table(path: str) -> None:
+    """Install the bin table of an autotuner JSON file."""
+    import json
+    with open(path) as f:
+        t = json.load(f)
+    set_bins([(b["m_hi"], b["packed"], b["lanes"]) for b in t["bins"]])
 
 
 def reserve(max_pairs: int, stream=None):

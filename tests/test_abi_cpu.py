@@ -29,8 +29,8 @@ def lib():
 def test_header_declares_the_boundary():
     names = _declared_functions()
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
-              "salo_error_count", "salo_last_timing", "salo_last_error", "salo_release",
-              "salo_version"]:
+              "salo_error_count", "salo_last_timing", "salo_set_bins", "salo_get_bins",
+              "salo_last_error", "salo_release", "salo_version"]:
         assert n in names
 
 
@@ -94,3 +94,26 @@ def test_bad_options(lib):
 
 def test_too_many_pairs(lib):
     assert _call(1 << 31) == -1
+
+
+def test_bin_table_roundtrip(lib):
+    default = salo.get_bins()
+    assert default[-1][0] == 65535 and len(default) >= 2
+    table = [(100, 1, 1), (1000, 1, 4), (65535, 1, 16), (65535, 0, 8)]
+    salo.set_bins(table)
+    assert salo.get_bins() == table
+    salo.set_bins(None)
+    assert salo.get_bins() == default
+
+
+@pytest.mark.parametrize("table", [
+    [(100, 1, 3), (65535, 1, 4), (65535, 0, 8)],          # lanes not a power of two
+    [(100, 1, 1), (50, 1, 4), (65535, 1, 4), (65535, 0, 8)],  # m_hi decreasing
+    [(100, 1, 1), (65535, 0, 8)],                          # 16-bit kind not closed
+    [(65535, 1, 1)],                                       # no 32-bit kind
+])
+def test_bad_bin_tables(lib, table):
+    before = salo.get_bins()
+    with pytest.raises(salo.SaloError):
+        salo.set_bins(table)
+    assert salo.get_bins() == before

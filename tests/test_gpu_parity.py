@@ -13,7 +13,7 @@ pytestmark = pytest.mark.gpu
 
 SCORING = (1, -4, 6, 1)
 PLAIN_VARIANTS = [(1, 16), (2, 16), (4, 16), (8, 16), (16, 16), (32, 16), (64, 16),
-                  (2, 8), (4, 8), (8, 8), (16, 8)]
+                  (2, 8), (4, 8), (8, 8), (16, 8), (1, 32), (2, 32), (8, 32), (64, 8)]
 
 
 def _say(*a):
@@ -161,8 +161,8 @@ def test_invalid_pairs_are_flagged(dev):
         assert np.array_equal(got[k][ok], want[k][ok])
 
 
-@pytest.mark.parametrize("lanes", [2, 4, 8, 16, 32, 64])
-@pytest.mark.parametrize("cols", [8, 16])
+@pytest.mark.parametrize("lanes", [1, 2, 4, 8, 16, 32, 64])
+@pytest.mark.parametrize("cols", [8, 16, 32])
 def test_persistent_forced_widths(dev, lanes, cols):
     b = _edge_batch()
     want = oracle_align(b)
@@ -204,3 +204,33 @@ def test_mixed_sample(dev):
     want = oracle_align(b)
     _say("mixed 6000 pairs default")
     assert_same(b, gpu_align(b), want, "mixed 6000")
+
+
+def test_bin_table_does_not_change_results(dev):
+    from paper_2301_09310_amd import salo
+    b = I.random_pairs(41, 2000, 2500, related=0.6)
+    want = oracle_align(b)
+    before = salo.get_bins()
+    try:
+        for table in ([(300, 1, 64), (65535, 1, 1), (65535, 0, 2)],
+                      [(50, 1, 8), (100, 1, 1), (400, 1, 32), (65535, 1, 4), (500, 0, 64),
+                       (65535, 0, 1)]):
+            salo.set_bins(table)
+            _say("bin table", table)
+            assert_same(b, gpu_align(b), want, "table %s" % (table,))
+            assert_same(b, gpu_align(b, force_int32=True), want, "table %s int32" % (table,))
+    finally:
+        salo.set_bins(None)
+    assert salo.get_bins() == before
+
+
+def test_bin_boundaries_with_both_cell_widths(dev):
+    """match=16 sends long pairs to 32-bit bins and short ones to 16-bit bins,
+    so units at the end of one bin sit next to pairs of a very different
+    length in the processing order."""
+    b = I.random_pairs(43, 400, 6000, related=0.6)
+    sc = (16, -20, 30, 5)
+    want = oracle_align(b, sc)
+    _say("random_pairs seed 43, lengths to 6000, scoring", sc)
+    assert_same(b, gpu_align(b, sc), want, "both widths")
+    assert_same(b, gpu_align(b, sc, cols=8), want, "both widths cols 8")
