@@ -39,6 +39,30 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
+def kernel_source_hash() -> str:
+    """sha256 of the DP kernel sources; profiler byte counts are only valid
+    for the kernel they were taken on."""
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("salo_kernels.hip", "salo_internal.h"):
+        with open(os.path.join(ROOT, "paper_2301_09310_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(workload: str):
+    """HBM bytes per DP launch for this kernel source and workload, from the
+    rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in traffic.json (scaled
+    by the plain-copy calibration); None when not measured for this source."""
+    path = os.path.join(ROOT, "paper_2301_09310_amd", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        table = json.load(f)
+    rec = table.get(kernel_source_hash(), {}).get(workload)
+    return None if rec is None else float(rec["bytes_per_launch"])
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -54,6 +78,17 @@ def main(argv=None) -> int:
     ap.add_argument("--cpu-sample", type=int, default=2_000_000)
     ap.add_argument("--parity-sample", type=int, default=3000)
     ap.add_argument("--compare-plain", action="store_true")
+    ap.add_argument("--serve", action="store_true",
+                    help="served stream: Poisson arrivals of 1-4096-pair requests drawn from "
+                         "the mixed workload; prints p50/p99 latency at 0.5x/0.8x/1.2x of the "
+                         "saturated request rate")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-warmup", type=int, default=100)
+    ap.add_argument("--serve-pool", type=int, default=1_000_000)
+    ap.add_argument("--serve-budget-gb", type=float, default=32.0)
+    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--graph", action="store_true",
+                    help="capture one step (plan + DP launches) in a HIP graph and time replays")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (a known-"
                          "traffic kernel for scaling the profiler's byte counters)")
@@ -86,6 +121,9 @@ def main(argv=None) -> int:
         log("copied %d bytes 3 times" % args.calibrate_copy)
         return 0
 
+    if args.serve:
+        return serve_bench(args)
+
     gen = I.WORKLOADS[args.workload]
     t0 = time.time()
     batch = gen(0, args.pairs) if args.pairs else gen(0)
@@ -104,6 +142,18 @@ def main(argv=None) -> int:
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
     torch.cuda.synchronize()
 
+    graph = None
+    if args.graph:
+        stream = torch.cuda.Stream()
+        with torch.cuda.stream(stream):
+            salo.reserve(n, stream=stream)
+            salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
+        stream.synchronize()
+        graph = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(graph, stream=stream):
+            salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
+        torch.cuda.synchronize()
+
     # timed region: K steps between events recorded on the launch stream;
     # the library also records events around its plan and DP kernels
     ev0 = torch.cuda.Event(enable_timing=True)
@@ -113,11 +163,22 @@ def main(argv=None) -> int:
     wall0 = time.perf_counter()
     ev0.record(stream)
     for _ in range(args.steps):
+        if graph is not None:
+            with torch.cuda.stream(stream):     # replays run on the current stream
+                graph.replay()
+            continue
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, timing=True, **opts)
         a, b = salo.last_timing(stream)
         plan_ms.append(a)
         dp_ms.append(b)
     ev1.record(stream)
+    if graph is not None:
+        # kernel durations of one replayed step, from a separate timed call
+        torch.cuda.synchronize()
+        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, timing=True, **opts)
+        a, b = salo.last_timing(stream)
+        plan_ms.append(a)
+        dp_ms.append(b)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = ev0.elapsed_time(ev1)
@@ -163,10 +224,12 @@ def main(argv=None) -> int:
     kern_ms = float(np.mean(dp_ms))
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TOPS[dtype]
+    traffic = measured_traffic(args.workload)
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
-            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": None,
+            "unit": "TOP/s", "frac": round(achieved / peak, 4), "traffic": traffic,
             "kernel": ("plain_kernel" if args.mode == "plain" else "persistent_kernel"),
-            "kernel_ms": round(kern_ms, 4), "ops_per_cell": OPS_PER_CELL}
+            "kernel_ms": round(kern_ms, 4), "ops_per_cell": OPS_PER_CELL,
+            "traffic_unit": "bytes per launch", "kernel_source": kernel_source_hash()}
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -191,7 +254,7 @@ def main(argv=None) -> int:
                    "scoring": list(SCORING), "mode": args.mode, "lanes": args.lanes,
                    "cols": args.cols, "parity": "bit-exact on %d sampled pairs" % k
                    if parity_ok else "MISMATCH on sampled pairs",
-                   "plan_ms": round(float(np.mean(plan_ms)), 4),
+                   "plan_ms": round(float(np.mean(plan_ms)), 4), "graph": bool(args.graph),
                    "dp_ms": round(kern_ms, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
@@ -199,6 +262,59 @@ def main(argv=None) -> int:
     }
     print(json.dumps(rec), flush=True)
     return 0 if parity_ok else 1
+
+
+def serve_bench(args) -> int:
+    """p50/p99 request latency of the served stream at fixed offered rates."""
+    from oracle import oracle as O
+    from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import serve as S
+    t0 = time.time()
+    pool = I.mixed(0, args.serve_pool)
+    log("serve pool: %d mixed pairs in %.1fs" % (pool.n_pairs, time.time() - t0))
+    n = args.serve_warmup + args.serve_requests
+    sizes = S.request_sizes(n, 1)
+    budget = int(args.serve_budget_gb * (1 << 30))
+    ex = S.GpuExecutor(n_streams=args.serve_streams, scoring=SCORING)
+    ex.reserve(int(sizes.max()))
+
+    def run(rate):
+        arr = np.zeros(n) if rate is None else S.poisson_arrivals(n, rate, 1)
+        reqs = S.split_requests(pool, sizes, arr)
+        st = S.Server(ex, budget_bytes=budget).run(reqs, warmup=args.serve_warmup)
+        return reqs, st.summary()
+
+    reqs, sat = run(None)              # all requests at once: saturated rate
+    log("saturated: %s" % json.dumps(sat))
+    rate_sat = sat["requests_per_s"]
+    # parity: a sample of served requests against the oracle
+    rng = np.random.default_rng(2)
+    ok = True
+    for r in rng.choice(reqs[args.serve_warmup:], size=20, replace=False):
+        b = r.batch
+        want = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, SCORING)
+        ok &= all(np.array_equal(g.astype(np.int64), w) for g, w in zip(r.result, want))
+    runs = {}
+    for f in (0.5, 0.8, 1.2):
+        _, summ = run(f * rate_sat)
+        runs["%.1fx" % f] = {"offered_rps": round(f * rate_sat, 2),
+                              "p50_ms": round(summ["p50_ms"], 3),
+                              "p99_ms": round(summ["p99_ms"], 3),
+                              "gcups": round(summ["gcups"], 1),
+                              "max_inflight": summ["max_inflight"]}
+        log("%.1fx: %s" % (f, json.dumps(runs["%.1fx" % f])))
+    rec = {"metric": METRIC, "value": runs["0.8x"]["p99_ms"], "unit": "ms (p99 at 0.8x)",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "u16x2",
+           "config": {"workload": "served mixed requests", "requests": args.serve_requests,
+                      "warmup_requests": args.serve_warmup, "pairs_per_request": "U{1..4096}",
+                      "pool_pairs": pool.n_pairs, "budget_gb": args.serve_budget_gb,
+                      "streams": args.serve_streams,
+                      "parity": "bit-exact on 20 sampled requests" if ok else "MISMATCH"},
+           "saturated": {"requests_per_s": round(rate_sat, 2), "gcups": round(sat["gcups"], 1),
+                         "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3)},
+           "rates": runs}
+    print(json.dumps(rec), flush=True)
+    return 0 if ok else 1
 
 
 if __name__ == "__main__":

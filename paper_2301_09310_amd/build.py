@@ -28,7 +28,7 @@ SOURCES = ["salo_kernels.hip", "salo_plan.hip", "salo_host.cpp"]
 
 
 def _compile(src: str, obj: str) -> None:
-    path = os.path.join(CSRC, src)
+    path = src if os.path.isabs(src) else os.path.join(CSRC, src)
     cmd = [HIPCC] + COMMON
     if src.endswith(".hip"):
         cmd += DEVICE + ["-x", "hip"]
@@ -36,22 +36,29 @@ def _compile(src: str, obj: str) -> None:
     subprocess.run(cmd, check=True)
 
 
-def build(jobs: int = 4, verbose: bool = True) -> str:
+def build(jobs: int = 4, verbose: bool = True, out: str | None = None,
+          csrc: str | None = None) -> str:
+    """Compile the sources in `csrc` (default: the package's csrc/) into
+    `out` (default: the package's libsalo.so)."""
+    global CSRC
+    if csrc:
+        CSRC = csrc
+    target = out or LIB
     srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
     tmp = tempfile.mkdtemp(prefix="salo_build_")
     try:
         objs = [os.path.join(tmp, s + ".o") for s in srcs]
         with ThreadPoolExecutor(max_workers=max(1, jobs)) as ex:
             list(ex.map(lambda so: _compile(*so), zip(srcs, objs)))
-        out_tmp = LIB + ".tmp%d" % os.getpid()
+        out_tmp = target + ".tmp%d" % os.getpid()
         subprocess.run([HIPCC, "-shared", "-fPIC", "--offload-arch=" + ARCH,
                         "-o", out_tmp] + objs, check=True)
-        os.replace(out_tmp, LIB)
+        os.replace(out_tmp, target)
     finally:
         shutil.rmtree(tmp, ignore_errors=True)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", target)
+    return target
 
 
 def main(argv=None) -> int:

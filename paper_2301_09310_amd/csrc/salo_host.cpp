@@ -135,9 +135,9 @@ salo_status_t ensure_plan(Workspace &ws, int64_t n_pairs, hipStream_t stream) {
 // ranges double from bin to bin; the built-in widths come from the
 // autotuner's sweep on one MI355X and can be replaced with salo_set_bins.
 const salo_bin_t kDefaultBins[] = {
-    {64, 1, 1, 0},   {128, 1, 2, 0},  {256, 1, 2, 0},   {512, 1, 4, 0},
-    {1024, 1, 8, 0}, {2048, 1, 16, 0}, {4096, 1, 32, 0}, {65535, 1, 64, 0},
-    {1024, 0, 4, 0}, {65535, 0, 16, 0},
+    {64, 1, 2, 0},    {128, 1, 2, 0},   {256, 1, 4, 0},   {512, 1, 8, 0},
+    {1024, 1, 64, 0}, {2048, 1, 32, 0}, {4096, 1, 64, 0}, {65535, 1, 64, 0},
+    {1024, 0, 32, 0}, {65535, 0, 64, 0},
 };
 
 std::mutex g_bins_mu;

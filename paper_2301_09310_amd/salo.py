@@ -53,7 +53,7 @@ def load(path: str | None = None):
     with _lock:
         if _lib is not None and path is None:
             return _lib
-        p = path or LIB_PATH
+        p = path or os.environ.get("SALO_LIB") or LIB_PATH
         if not os.path.exists(p):
             raise ImportError("libsalo.so not found at %s; build it with "
                               "`python -m paper_2301_09310_amd.build`" % p)

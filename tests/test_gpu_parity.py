@@ -234,3 +234,38 @@ def test_bin_boundaries_with_both_cell_widths(dev):
     _say("random_pairs seed 43, lengths to 6000, scoring", sc)
     assert_same(b, gpu_align(b, sc), want, "both widths")
     assert_same(b, gpu_align(b, sc, cols=8), want, "both widths cols 8")
+
+
+def test_graph_capture_replays(dev):
+    """Plan + persistent launches captured in a HIP graph: every replay, with
+    eager work and synchronisations in between, equals the eager result."""
+    import torch
+    from paper_2301_09310_amd import salo
+    b1 = I.random_pairs(51, 3000, 700, related=0.6)
+    # same shapes, other content: swap A<->C and G<->T in every query
+    b2 = I.Batch(b1.q_seqs ^ np.uint8(0x55), b1.q_offsets, b1.t_seqs, b1.t_offsets)
+    want1, want2 = oracle_align(b1), oracle_align(b2)
+    s = torch.cuda.Stream()
+    q, qo, t, to = salo.to_device(b1)
+    out = tuple(torch.empty(b1.n_pairs, dtype=torch.int32, device="cuda") for _ in range(3))
+    with torch.cuda.stream(s):
+        salo.reserve(b1.n_pairs, stream=s)
+        salo.align_batch(q, qo, t, to, out=out, stream=s)     # warm-up on the capture stream
+    s.synchronize()
+    _say("graph capture")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        salo.align_batch(q, qo, t, to, out=out, stream=s)
+    for rep in range(4):
+        src = b1 if rep % 2 == 0 else b2
+        d = salo.to_device(src)
+        for x, y in zip((q, qo, t, to), d):
+            x.copy_(y)
+        for o in out:
+            o.fill_(-7)                                      # eager work between replays
+        torch.cuda.synchronize()
+        _say("graph replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        got = tuple(x.cpu().numpy().astype(np.int64) for x in out)
+        assert_same(src, got, want1 if rep % 2 == 0 else want2, "replay %d" % rep)
