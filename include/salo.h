@@ -93,12 +93,15 @@ typedef struct {
     int32_t waves_per_cu;   /* grid size in resident waves per CU; 0 = default */
     int32_t timing;         /* 1: record events around the plan and DP kernels
                                (see salo_last_timing); 0 = off */
-    int32_t reserved[2];    /* must be 0 */
+    int32_t no_f16;         /* 1: never use binary16 cells (16-bit integer or
+                               32-bit cells only); results are identical */
+    int32_t reserved;       /* must be 0 */
 } salo_options_t;
 
 /* One length bin of the persistent mode: pairs whose query length is at
  * most m_hi (and above the previous bin's m_hi of the same kind), with
- * 16-bit cells (packed = 1) or 32-bit cells (packed = 0), run in lane
+ * 16-bit cells (packed = 1; binary16 or 16-bit integer cells, chosen per
+ * unit of work from its pairs' score bounds) or 32-bit cells (packed = 0), run in lane
  * groups of `lanes` lanes.  A pair whose target is too long for its bin's
  * width (more than 1024 * lanes bases) moves to the next bin of its kind. */
 typedef struct {

@@ -208,8 +208,8 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
-    for (int r : o.reserved)
-        if (r != 0) return fail(SALO_ERR_INVALID, "salo_options_t.reserved must be 0");
+    if (o.reserved != 0) return fail(SALO_ERR_INVALID, "salo_options_t.reserved must be 0");
+    if (o.no_f16 != 0 && o.no_f16 != 1) return fail(SALO_ERR_INVALID, "no_f16 must be 0 or 1");
     if (o.mode < SALO_MODE_AUTO || o.mode > SALO_MODE_PERSISTENT)
         return fail(SALO_ERR_INVALID, "unknown mode");
     if (o.waves_per_cu < 0 || o.waves_per_cu > 32)
@@ -240,6 +240,8 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
     p.errors = ws->errors;
     p.force_int32 = o.force_int32 ? 1 : 0;
     p.packed_ok = scoring_packed_ok(scoring.match, scoring.mismatch) ? 1 : 0;
+    p.half_ok = !o.no_f16 && scoring_half_ok(scoring.match, scoring.mismatch,
+                                             scoring.gap_open, scoring.gap_extend);
     p.bins = ws->bins;
     p.unit_counter = ws->counters;
     p.total_units = ws->counters + 1;

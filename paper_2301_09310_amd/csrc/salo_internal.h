@@ -69,6 +69,7 @@ struct KParams {
     unsigned long long *errors;    // invalid-pair counter
     int32_t force_int32;
     int32_t packed_ok;             // scoring admits 16-bit packed cells
+    int32_t half_ok;               // scoring admits binary16 cells (and no_f16 is off)
     // persistent mode
     BinDesc *bins;                 // kMaxBins entries (device)
     int32_t n_bins;
@@ -79,6 +80,48 @@ struct KParams {
 // Scoring admits the packed 16-bit path (match + |mismatch| fits a byte).
 inline bool scoring_packed_ok(int32_t match, int32_t mismatch) {
     return match - mismatch <= 255;
+}
+
+// Largest value a packed 16-bit cell may take: below 0x7C00 every cell
+// value, read as a binary16 number, is finite and non-negative, so the
+// packed half-precision maximum orders cells exactly like integers.
+constexpr int32_t kPackedLimit = 0x7BFF;
+
+// A pair fits 16-bit cells when its best score plus one substitution step
+// stays within kPackedLimit (every H, E, F and diagonal sum is below that).
+__host__ __device__ inline bool packed_bound_ok(int32_t match, int32_t mismatch, int64_t mn) {
+    return (int64_t)match * (mn + 1) - (int64_t)mismatch <= kPackedLimit;
+}
+
+// binary16 holds every integer of magnitude <= 2048 exactly.  A pair runs
+// in binary16 cells when its best score is at most that: every
+// non-negative value the recurrence forms is then exact, and a negative
+// one, rounded or not, stays negative and loses every maximum against the
+// zero-clamped E.
+constexpr int32_t kHalfExact = 2048;
+__host__ __device__ inline bool half_bound_ok(int32_t match, int64_t mn) {
+    return (int64_t)match * mn <= kHalfExact;
+}
+
+// The binary16 row table stores one byte per score: the high byte of its
+// binary16 encoding, so the low byte must be 0.  That holds for integers
+// with at most three significant bits (1..8, 10, 12, 14, 16, 20, ...);
+// alpha and beta must be exact too.
+inline bool half_value_ok(int32_t v) {
+    const uint32_t a = (uint32_t)(v < 0 ? -v : v);
+    if (a > (uint32_t)kHalfExact) return false;
+    uint32_t top = a;
+    int drop = 0;
+    while (top >= 8u) {
+        top >>= 1;
+        ++drop;
+    }
+    return (top << drop) == a;
+}
+inline bool scoring_half_ok(int32_t match, int32_t mismatch, int32_t gap_open,
+                            int32_t gap_extend) {
+    return half_value_ok(match) && half_value_ok(mismatch) &&
+           (int64_t)gap_open + gap_extend <= kHalfExact && gap_extend <= kHalfExact;
 }
 
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,

@@ -18,7 +18,9 @@
 //    next chunk (the role of the paper's lazy spill, Section IV-B).
 //  * Cells are 16-bit where a pair's score bound allows it: two pairs share
 //    a group, one in each half of every VGPR, and every DP operation is one
-//    packed instruction (v_pk_add_u16 / v_pk_sub_u16 clamp / v_pk_max_u16).
+//    packed instruction (v_pk_add_u16 / v_pk_sub_u16 clamp / v_pk_max_u16,
+//    and v_pk_maximum3_f16 as an exact three-way integer maximum: see
+//    pmax3).
 //    E and F are clamped at 0; any E/F value <= 0 yields the same H, so
 //    unsigned saturating subtraction is exact.  The substitution score comes
 //    from one v_perm_b32 per cell pair: a per-row byte table (match -
@@ -54,6 +56,33 @@ __device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
 }
 __device__ __forceinline__ uint32_t pmax(uint32_t a, uint32_t b) {
     return as_u(__builtin_elementwise_max(as_v(a), as_v(b)));
+}
+// Maximum of three packed cell pairs.  Cell values stay in [0, 0x7BFF]
+// (kPackedLimit), where reading the bits as binary16 gives finite,
+// non-negative numbers (denormals included, which the kernels keep) in the
+// same order as the integers; the half-precision maximum returns one of
+// its operands unchanged, so one v_pk_maximum3_f16 is an exact integer
+// max3 for both halves.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pmax3(uint32_t a, uint32_t b, uint32_t c) {
+    const f16x2 x = __builtin_bit_cast(f16x2, a);
+    const f16x2 y = __builtin_bit_cast(f16x2, b);
+    const f16x2 z = __builtin_bit_cast(f16x2, c);
+    return __builtin_bit_cast(
+        uint32_t, __builtin_elementwise_maximum(__builtin_elementwise_maximum(x, y), z));
+}
+// binary16 cells: exact integer arithmetic on values of magnitude <= 2048
+__device__ __forceinline__ uint32_t hadd(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t,
+                              __builtin_bit_cast(f16x2, a) + __builtin_bit_cast(f16x2, b));
+}
+__device__ __forceinline__ uint32_t hmax(uint32_t a, uint32_t b) {
+    return __builtin_bit_cast(uint32_t, __builtin_elementwise_maximum(
+                                            __builtin_bit_cast(f16x2, a),
+                                            __builtin_bit_cast(f16x2, b)));
+}
+__device__ __forceinline__ int32_t half_bits_to_int(uint32_t v) {
+    return (int32_t)(float)__builtin_bit_cast(_Float16, (uint16_t)v);
 }
 __device__ __forceinline__ int max3i(int a, int b, int c) {
     return max(max(a, b), c);
@@ -190,15 +219,21 @@ __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr
     P.out_tend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF)) : -1;
 }
 
+// Cell types of a unit: 32-bit integers (one pair per group), or two pairs
+// per group in the 16-bit halves of every register, as saturating 16-bit
+// integers or as binary16 numbers.
+enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
+
 // One unit: G = 64/W groups; each group aligns NPG pairs (2 packed, 1 wide).
 // pos0: first position (in processing order) of the unit's pairs.
 // [g0, g0 + gn): the groups processed in this pass (all G normally; fewer
 // when the unit's boundary columns do not fit one slot together).
-template <int K, bool PK>
+template <int K, int CT>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
                          uint32_t *slot, uint32_t *lds_saved) {
     const int G = kWave / W;
+    constexpr bool PK = CT != kCellWide;
     constexpr int NPG = PK ? 2 : 1;
     static_assert(K % 4 == 0 && K <= 32, "K must be 4..32, multiple of 4");
     const int lane = threadIdx.x & (kWave - 1);
@@ -237,6 +272,16 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     const uint32_t NB2 = (uint32_t)(-b) * 0x10001u;
     const uint32_t AL2 = (uint32_t)alpha * 0x10001u;
     const uint32_t BE2 = (uint32_t)beta * 0x10001u;
+    // binary16 cells: -alpha and -beta in both halves; the row table holds
+    // the high byte of match or mismatch as binary16 (their low bytes are 0)
+    const uint32_t hm = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)a) >> 8;
+    const uint32_t hx = (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)b) >> 8;
+    const uint32_t MM4 = hx * 0x01010101u;       // every base a mismatch
+    const uint32_t XM = hm ^ hx;                 // flips one slot to match
+    const uint32_t NAL2 =
+        (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(-alpha)) * 0x10001u;
+    const uint32_t NBE2 =
+        (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(-beta)) * 0x10001u;
 
     // per-lane target stream geometry (per pair of the group)
     int64_t twi[NPG];
@@ -278,7 +323,13 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                             ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u) : 12u;
                     const uint32_t sB = (col0 + k < pr[1].m)
                                             ? (4u + ((qw[1][k >> 4] >> (2 * (k & 15))) & 3u)) : 12u;
-                    SEL[k] = sA | (sB << 16) | 0x0C000C00u;
+                    // 16-bit integers: table byte low, 0 high; binary16:
+                    // 0 low, table byte high (a column past the query's end
+                    // selects 0 in both bytes)
+                    if constexpr (CT == kCellU16)
+                        SEL[k] = sA | (sB << 16) | 0x0C000C00u;
+                    else
+                        SEL[k] = (sA << 8) | (sB << 24) | 0x000C000Cu;
                 } else {
                     SEL[k] = (col0 + k < pr[0].m) ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u)
                                                   : 5u;
@@ -352,7 +403,29 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     uint32_t e = ein;
                     uint32_t hd = hprev;
                     uint32_t rowmax = 0;
-                    if constexpr (PK) {
+                    if constexpr (CT == kCellF16) {
+                        // S(i,j) = hd + table value, as binary16 numbers;
+                        // E is clamped at 0 (so H >= 0 needs no fourth
+                        // operand); F may go negative, down to -alpha
+                        const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
+                        const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
+                        const uint32_t TA = i < pr[0].n ? (MM4 ^ (XM << (bA << 3))) : 0u;
+                        const uint32_t TB = i < pr[1].n ? (MM4 ^ (XM << (bB << 3))) : 0u;
+#pragma unroll
+                        for (int k = 0; k < K; ++k) {
+                            const uint32_t T = __builtin_amdgcn_perm(TB, TA, SEL[k]);
+                            const uint32_t d = hadd(hd, T);
+                            hd = H[k];
+                            const uint32_t f = F[k];
+                            const uint32_t hh = pmax3(d, f, e);
+                            H[k] = hh;
+                            const uint32_t ha = hadd(hh, NAL2);
+                            F[k] = hmax(hadd(f, NBE2), ha);
+                            e = pmax3(hadd(e, NBE2), ha, 0u);
+                            if (k & 1)
+                                rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
+                        }
+                    } else if constexpr (CT == kCellU16) {
                         const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
                         const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
                         const uint32_t TA = i < pr[0].n ? (KC << (bA << 3)) : 0u;
@@ -363,12 +436,14 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             const uint32_t d = psub(padd(hd, T), NB2);
                             hd = H[k];
                             const uint32_t f = F[k];
-                            const uint32_t hh = pmax(pmax(d, f), e);
+                            const uint32_t hh = pmax3(d, f, e);
                             H[k] = hh;
                             const uint32_t ha = psub(hh, AL2);
                             F[k] = pmax(psub(f, BE2), ha);
-                            rowmax = k == 0 ? hh : pmax(rowmax, hh);
                             e = pmax(psub(e, BE2), ha);
+                            // row maximum two columns at a time
+                            if (k & 1)
+                                rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
                         }
                     } else {
                         const uint32_t tb = i < pr[0].n ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
@@ -437,7 +512,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                            : my_saved[k];
                     if (hv == v) kk = k;
                 }
-                best[h].offer((int32_t)v, crow[h], col0 + kk);
+                best[h].offer(CT == kCellF16 ? half_bits_to_int(v) : (int32_t)v, crow[h],
+                              col0 + kk);
             }
         }
         // the slot's column becomes the next chunk's input: make the last
@@ -453,19 +529,22 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     }
 }
 
-// A unit is packed-eligible when every pair's score bound stays below 2^15.
-__device__ __forceinline__ bool unit_packed_ok(const KParams &P, int64_t pos0, int npairs) {
-    if (!P.packed_ok || P.force_int32) return false;
+// The narrowest cell type every pair of the unit admits.
+__device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, int npairs) {
+    if (!P.packed_ok || P.force_int32) return kCellWide;
     const int lane = threadIdx.x & (kWave - 1);
-    bool ok = true;
+    bool ok16 = true, okh = P.half_ok != 0;
     for (int k = lane; k < npairs; k += kWave) {
         const PairRef r = load_pair(P, pos0 + k, pos0 + npairs, true);
         if (r.id >= 0 && !r.invalid) {
             const int64_t mn = min(r.m, r.n);
-            if ((int64_t)P.match * (mn + 1) - (int64_t)P.mismatch > 32767) ok = false;
+            if (!packed_bound_ok(P.match, P.mismatch, mn)) ok16 = false;
+            if (!half_bound_ok(P.match, mn)) okh = false;
         }
     }
-    return __builtin_amdgcn_readfirstlane(__ballot(!ok) == 0ull ? 1 : 0) != 0;
+    const bool all16 = __ballot(!ok16) == 0ull;
+    const bool allh = __ballot(!okh) == 0ull;
+    return __builtin_amdgcn_readfirstlane(all16 ? (allh ? kCellF16 : kCellU16) : kCellWide);
 }
 
 template <int K>
@@ -486,15 +565,20 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     // instantiation keeps run_unit inlined.
     const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(R, 1)));
     const int passes = (G + fit - 1) / fit;
-    if (unit_packed_ok(P, pos0, npairs)) {
+    const int ct = unit_cell_type(P, pos0, npairs);
+    if (ct == kCellF16) {
         for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, true>(P, qs, ts, pos0, pos0 + npairs, ps * fit, min(fit, G - ps * fit),
-                              W, slot, lds);
+            run_unit<K, kCellF16>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
+                                  min(fit, G - ps * fit), W, slot, lds);
+    } else if (ct == kCellU16) {
+        for (int ps = 0; ps < passes; ++ps)
+            run_unit<K, kCellU16>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
+                                  min(fit, G - ps * fit), W, slot, lds);
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;
-            run_unit<K, false>(P, qs, ts, pos0 + (int64_t)half * G, pos0 + npairs, ps * fit,
-                               min(fit, G - ps * fit), W, slot, lds);
+            run_unit<K, kCellWide>(P, qs, ts, pos0 + (int64_t)half * G, pos0 + npairs,
+                                   ps * fit, min(fit, G - ps * fit), W, slot, lds);
         }
     }
 }

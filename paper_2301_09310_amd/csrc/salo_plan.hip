@@ -40,12 +40,9 @@ __device__ __forceinline__ PairLen pair_len(const KParams &P, int64_t p) {
     return {valid ? m : 0, valid ? n : 0};
 }
 
-// 16-bit cells hold every value of a pair whose best score plus one
-// substitution step stays below 2^15.
 __device__ __forceinline__ bool pair_packed(const KParams &P, int64_t m, int64_t n) {
     if (!P.packed_ok || P.force_int32) return false;
-    const int64_t mn = m < n ? m : n;
-    return (int64_t)P.match * (mn + 1) - (int64_t)P.mismatch <= 32767;
+    return packed_bound_ok(P.match, P.mismatch, m < n ? m : n);
 }
 
 // First bin of the pair's kind (16- or 32-bit) whose query range holds m

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("cols", ctypes.c_int32), ("force_int32", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("reserved", ctypes.c_int32 * 2)]
+                ("no_f16", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Bin(ctypes.Structure):
@@ -99,9 +99,10 @@ def _stream_handle(stream):
 
 
 def make_options(mode="auto", lanes=0, cols=0, force_int32=False, waves_per_cu=0,
-                 timing=False):
+                 timing=False, no_f16=False):
     o = Options()
     o.timing = 1 if timing else 0
+    o.no_f16 = 1 if no_f16 else 0
     o.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
     o.lanes, o.cols = int(lanes), int(cols)
     o.force_int32 = 1 if force_int32 else 0
@@ -117,7 +118,7 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
     int64 CUDA tensors of n_pairs+1 entries.  Returns (score, q_end, t_end)
     int32 CUDA tensors (or fills `out`, a triple of such tensors).  Keyword
     options: mode ('auto' | 'plain' | 'persistent'), lanes, cols,
-    force_int32, waves_per_cu, timing.
+    force_int32, no_f16, waves_per_cu, timing.
     """
     import torch
     lib = load()

@@ -1,18 +1,30 @@
 """Serving loop: continuous batching of alignment requests on one GPU.
 
-Requests (batches of pairs of any size) arrive over time.  The loop keeps
-arrived requests in FIFO order and admits the head whenever its HBM
-footprint fits the budget next to the requests already on the GPU and an
-execution slot (a HIP stream) is free.  Each admitted request is copied to
-the device and aligned on its own stream with the library's default
-(persistent, length-binned) path, so requests that arrive while others run
-start as soon as slots and memory free up and overlap on the device.
-Results come back to pinned host memory; completion is observed through a
-HIP event per request.  Latency is measured from the request's scheduled
+Requests (batches of pairs of any size) arrive over time and wait in FIFO
+order.  Whenever an execution slot is free, the loop forms one launch from
+the head of the queue: every waiting request that still fits the launch's
+pair and byte capacity and the HBM budget next to the work already on the
+GPU.  A launch is one call of the library's default (persistent,
+length-binned) path over the merged pairs of its requests, on the slot's
+own HIP stream.  So at low load a request starts alone as soon as it
+arrives, and under load the requests that arrived while earlier launches
+ran are aligned together: their pairs share one work queue and one
+length-binned schedule, and the new launch overlaps the tail of the
+running ones on the device.
+
+Merging needs no repacking: each request's packed streams are copied
+byte-aligned into the slot's pinned staging buffers, its offsets are
+shifted by the byte position, and one pad pair after each request (its
+query and target are the few padding bases up to the next request's
+first sequences) keeps the merged offsets contiguous; its output is
+dropped.  Staging and device buffers are
+allocated once per slot, so the steady state allocates nothing.  Results
+return to pinned host memory; completion is observed through one HIP
+event per launch.  Latency is measured from each request's scheduled
 arrival (open loop, so a slow server cannot hide queueing delay).
 
-The control plane (admission, FIFO order, accounting) only talks to an
-executor object, so it can be exercised on the CPU with a fake executor
+The control plane (admission, FIFO order, launch forming, accounting) only
+talks to an executor object, so it runs on the CPU with a fake executor
 and a fake clock.
 """
 from __future__ import annotations
@@ -30,10 +42,10 @@ class Request:
     arrival: float                     # scheduled arrival time (seconds)
     t_admit: float = -1.0
     t_done: float = -1.0
-    status: str = "pending"            # pending | running | done | rejected | failed
+    status: str = "pending"            # pending | running | done | rejected
     result: tuple | None = None        # (score, q_end, t_end) numpy int32
-    handle: object = None
     footprint: int = 0
+    launch: int = -1                   # index of the launch that ran it
 
     @property
     def latency(self) -> float:
@@ -42,15 +54,52 @@ class Request:
 
 def footprint_bytes(batch) -> int:
     """Device bytes one request holds while in flight: packed sequences,
-    offsets, outputs, and the plan's per-pair buffers (keys and order)."""
-    n = batch.n_pairs
+    offsets (one more entry for the pad pair), outputs, and the plan's
+    per-pair buffers (keys and order)."""
+    n = batch.n_pairs + 1
     return int(batch.q_seqs.nbytes + batch.t_seqs.nbytes + 16 * (n + 1) + 12 * n + 6 * n)
 
 
-class GpuExecutor:
-    """Runs each request on its own HIP stream through the library."""
+class Merged:
+    """Byte-aligned concatenation of several requests' packed pairs, with
+    one pad pair after each request (see the module docstring)."""
 
-    def __init__(self, n_streams: int = 4, scoring=(1, -4, 6, 1), device="cuda", **options):
+    def __init__(self, batches):
+        self.batches = list(batches)
+        self.q_bytes = sum(b.q_seqs.nbytes for b in self.batches)
+        self.t_bytes = sum(b.t_seqs.nbytes for b in self.batches)
+        self.n_pairs = sum(b.n_pairs + 1 for b in self.batches)
+
+    def fill(self, q, qo, t, to):
+        """Write the merged streams into q/t (uint8) and the offsets into
+        qo/to (int64, n_pairs + 1 entries); returns each request's first
+        output index.  The pad pair after a request spans the padding bases
+        between its last sequences and the next request's first ones (a few
+        bases of each stream; its result is not used)."""
+        starts = []
+        bq = bt = p = 0
+        for b in self.batches:
+            n = b.n_pairs
+            q[bq:bq + b.q_seqs.nbytes] = b.q_seqs
+            t[bt:bt + b.t_seqs.nbytes] = b.t_seqs
+            qo[p:p + n + 1] = b.q_offsets + 4 * bq
+            to[p:p + n + 1] = b.t_offsets + 4 * bt
+            starts.append(p)
+            bq += b.q_seqs.nbytes
+            bt += b.t_seqs.nbytes
+            p += n + 1
+            qo[p] = 4 * bq
+            to[p] = 4 * bt
+        return starts
+
+
+class GpuExecutor:
+    """Runs launches on `n_slots` HIP streams, each with buffers sized for
+    `max_pairs` pairs and `max_bytes` packed bytes per sequence stream."""
+
+    def __init__(self, n_slots: int = 3, max_pairs: int = 1 << 17,
+                 max_bytes: int = 96 << 20, scoring=(1, -4, 6, 1), device="cuda",
+                 **options):
         import torch
         from paper_2301_09310_amd import salo
         salo.load()
@@ -58,45 +107,66 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.scoring = scoring
         self.options = options
-        self.streams = [torch.cuda.Stream(device=self.device) for _ in range(n_streams)]
-        self.free = list(range(n_streams))
+        self.max_pairs = int(max_pairs)
+        self.max_bytes = int(max_bytes)
+        self.slots = []
+        for _ in range(n_slots):
+            s = torch.cuda.Stream(device=self.device)
+            host = {"q": torch.empty(self.max_bytes, dtype=torch.uint8, pin_memory=True),
+                    "t": torch.empty(self.max_bytes, dtype=torch.uint8, pin_memory=True),
+                    "qo": torch.empty(self.max_pairs + 1, dtype=torch.int64, pin_memory=True),
+                    "to": torch.empty(self.max_pairs + 1, dtype=torch.int64, pin_memory=True),
+                    "out": torch.empty((3, self.max_pairs), dtype=torch.int32,
+                                       pin_memory=True)}
+            dev = {k: torch.empty_like(v, device=self.device) for k, v in host.items()}
+            salo.reserve(self.max_pairs, stream=s)
+            self.slots.append({"stream": s, "host": host, "dev": dev,
+                               "event": torch.cuda.Event()})
+        self.free = list(range(n_slots))
 
     @property
     def slots_free(self) -> int:
         return len(self.free)
 
-    def reserve(self, max_pairs: int):
-        for s in self.streams:
-            self.salo.reserve(max_pairs, stream=s)
+    def fits(self, n_pairs: int, q_bytes: int, t_bytes: int) -> bool:
+        """Whether a launch of this size fits one slot."""
+        return n_pairs <= self.max_pairs and q_bytes <= self.max_bytes \
+            and t_bytes <= self.max_bytes
 
-    def submit(self, req: Request):
+    def submit(self, reqs):
         torch = self.torch
         k = self.free.pop()
-        s = self.streams[k]
-        b = req.batch
-        n = b.n_pairs
-        host_in = [torch.from_numpy(a).pin_memory() for a in
-                   (b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets)]
-        host_out = [torch.empty(n, dtype=torch.int32).pin_memory() for _ in range(3)]
+        sl = self.slots[k]
+        m = Merged([r.batch for r in reqs])
+        h, d, s = sl["host"], sl["dev"], sl["stream"]
+        n = m.n_pairs
+        starts = m.fill(h["q"].numpy(), h["qo"].numpy(), h["t"].numpy(), h["to"].numpy())
         with torch.cuda.stream(s):
-            dev_in = [x.to(self.device, non_blocking=True) for x in host_in]
-            dev_out = [torch.empty(n, dtype=torch.int32, device=self.device) for _ in range(3)]
-            self.salo.align_batch(*dev_in, self.scoring, out=dev_out, stream=s, **self.options)
-            for h, d in zip(host_out, dev_out):
-                h.copy_(d, non_blocking=True)
-            ev = torch.cuda.Event()
-            ev.record(s)
-        # keep every buffer alive until the event has passed
-        return (k, ev, host_in, dev_in, dev_out, host_out)
+            d["q"][:m.q_bytes].copy_(h["q"][:m.q_bytes], non_blocking=True)
+            d["t"][:m.t_bytes].copy_(h["t"][:m.t_bytes], non_blocking=True)
+            d["qo"][:n + 1].copy_(h["qo"][:n + 1], non_blocking=True)
+            d["to"][:n + 1].copy_(h["to"][:n + 1], non_blocking=True)
+            out = (d["out"][0, :n], d["out"][1, :n], d["out"][2, :n])
+            self.salo.align_batch(d["q"][:m.q_bytes], d["qo"][:n + 1], d["t"][:m.t_bytes],
+                                  d["to"][:n + 1], self.scoring, out=out, stream=s,
+                                  **self.options)
+            for c in range(3):
+                h["out"][c, :n].copy_(d["out"][c, :n], non_blocking=True)
+            sl["event"].record(s)
+        return (k, [(r, p) for r, p in zip(reqs, starts)])
 
     def poll(self, handle) -> bool:
-        return handle[1].query()
+        return self.slots[handle[0]]["event"].query()
 
     def collect(self, handle):
-        k, ev, _, _, _, host_out = handle
-        ev.synchronize()
+        k, parts = handle
+        sl = self.slots[k]
+        sl["event"].synchronize()
+        out = sl["host"]["out"].numpy()
+        res = [tuple(out[c, p:p + r.batch.n_pairs].copy() for c in range(3))
+               for r, p in parts]
         self.free.append(k)
-        return tuple(h.numpy().copy() for h in host_out)
+        return res
 
 
 @dataclass
@@ -107,45 +177,81 @@ class ServeStats:
     first_arrival: float = 0.0
     last_done: float = 0.0
     max_inflight_bytes: int = 0
-    max_inflight: int = 0
+    max_inflight: int = 0              # requests on the GPU at once
+    max_launches: int = 0              # launches on the GPU at once
+    launches: int = 0
+    launch_sizes: list = field(default_factory=list)   # requests per launch
     latencies: list = field(default_factory=list)
 
     def summary(self) -> dict:
         lat = np.array(self.latencies) if self.latencies else np.array([float("nan")])
         span = max(self.last_done - self.first_arrival, 1e-12)
+        sizes = np.array(self.launch_sizes) if self.launch_sizes else np.zeros(1)
         return {"completed": self.completed, "rejected": self.rejected,
                 "p50_ms": float(np.percentile(lat, 50) * 1e3),
                 "p99_ms": float(np.percentile(lat, 99) * 1e3),
                 "mean_ms": float(np.mean(lat) * 1e3),
                 "gcups": self.cells / span / 1e9,
                 "requests_per_s": self.completed / span,
+                "launches": self.launches,
+                "mean_requests_per_launch": float(sizes.mean()),
                 "max_inflight_bytes": self.max_inflight_bytes,
-                "max_inflight": self.max_inflight}
+                "max_inflight": self.max_inflight,
+                "max_launches": self.max_launches}
 
 
 class Server:
-    """Admission by HBM footprint, FIFO order, overlapping execution."""
+    """FIFO admission by HBM footprint into merged launches that overlap on
+    the device (continuous batching)."""
 
     def __init__(self, executor, budget_bytes: int, clock=time.perf_counter,
-                 sleep=time.sleep, poll_interval: float = 50e-6):
+                 sleep=time.sleep, poll_interval: float = 50e-6, progress=None,
+                 progress_every: float = 5.0):
         self.ex = executor
         self.budget = int(budget_bytes)
         self.clock = clock
         self.sleep = sleep
         self.poll_interval = poll_interval
+        self.progress = progress
+        self.progress_every = progress_every
+
+    def _form_launch(self, pending, in_bytes):
+        """Take requests from the head of the queue while the launch fits
+        one slot and the budget; returns (launch, rejected)."""
+        take, rejected = [], []
+        nb = q_b = t_b = fp = 0
+        while pending:
+            head = pending[0]
+            b = head.batch
+            alone_fits = self.ex.fits(b.n_pairs + 1, b.q_seqs.nbytes, b.t_seqs.nbytes) \
+                and head.footprint <= self.budget
+            if not alone_fits:
+                rejected.append(pending.pop(0))
+                continue
+            if not self.ex.fits(nb + b.n_pairs + 1, q_b + b.q_seqs.nbytes,
+                                t_b + b.t_seqs.nbytes) \
+                    or in_bytes + fp + head.footprint > self.budget:
+                break
+            take.append(pending.pop(0))
+            nb += b.n_pairs + 1
+            q_b += b.q_seqs.nbytes
+            t_b += b.t_seqs.nbytes
+            fp += head.footprint
+        return take, rejected
 
     def run(self, requests, warmup: int = 0) -> ServeStats:
-        """Serve `requests` (sorted by arrival, times relative to the start).
-        The first `warmup` requests are served but left out of the stats."""
+        """Serve `requests` (arrival times relative to the start).  The
+        first `warmup` requests by arrival are served but left out of the
+        stats."""
         reqs = sorted(requests, key=lambda r: r.arrival)
         t0 = self.clock()
         for r in reqs:
             r.arrival += t0
             r.footprint = footprint_bytes(r.batch)
         stats = ServeStats()
-        pending, inflight = [], []
-        nxt, in_bytes = 0, 0
-        done_count = 0
+        pending, inflight = [], []          # inflight: (handle, [requests])
+        nxt = in_bytes = done_count = 0
+        last_report = t0
         while done_count < len(reqs):
             now = self.clock()
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
@@ -153,39 +259,40 @@ class Server:
                 nxt += 1
             # completions
             still = []
-            for r in inflight:
-                if self.ex.poll(r.handle):
-                    r.result = self.ex.collect(r.handle)
-                    r.t_done = self.clock()
-                    r.status = "done"
-                    r.handle = None
-                    in_bytes -= r.footprint
-                    done_count += 1
+            for handle, group in inflight:
+                if self.ex.poll(handle):
+                    results = self.ex.collect(handle)
+                    t_done = self.clock()
+                    for r, res in zip(group, results):
+                        r.result, r.t_done, r.status = res, t_done, "done"
+                        in_bytes -= r.footprint
+                    done_count += len(group)
                 else:
-                    still.append(r)
+                    still.append((handle, group))
             inflight = still
-            # FIFO admission while the head fits
-            while pending:
-                head = pending[0]
-                if head.footprint > self.budget:
-                    head.status = "rejected"
-                    head.t_done = self.clock()
-                    pending.pop(0)
+            # form launches while slots are free
+            while pending and self.ex.slots_free > 0:
+                take, rejected = self._form_launch(pending, in_bytes)
+                for r in rejected:
+                    r.status, r.t_done = "rejected", self.clock()
                     done_count += 1
-                    continue
-                if self.ex.slots_free == 0 or in_bytes + head.footprint > self.budget:
+                if not take:
                     break
-                pending.pop(0)
-                head.t_admit = self.clock()
-                head.status = "running"
-                head.handle = self.ex.submit(head)
-                in_bytes += head.footprint
-                inflight.append(head)
+                t_admit = self.clock()
+                for r in take:
+                    r.t_admit, r.status, r.launch = t_admit, "running", stats.launches
+                    in_bytes += r.footprint
+                inflight.append((self.ex.submit(take), take))
+                stats.launches += 1
+                stats.launch_sizes.append(len(take))
                 stats.max_inflight_bytes = max(stats.max_inflight_bytes, in_bytes)
-                stats.max_inflight = max(stats.max_inflight, len(inflight))
+                stats.max_inflight = max(stats.max_inflight, sum(len(g) for _, g in inflight))
+                stats.max_launches = max(stats.max_launches, len(inflight))
+            if self.progress is not None and self.clock() - last_report >= self.progress_every:
+                last_report = self.clock()
+                self.progress("served %d/%d requests, %d launches, %d waiting"
+                              % (done_count, len(reqs), stats.launches, len(pending)))
             if done_count < len(reqs):
-                # nothing changed this turn: wait a little (next arrival or
-                # a completion)
                 wait = self.poll_interval
                 if not inflight and not pending and nxt < len(reqs):
                     wait = max(0.0, reqs[nxt].arrival - self.clock())

@@ -82,10 +82,10 @@ def test_misaligned_stream(lib):
 
 def test_bad_options(lib):
     o = salo.make_options()
-    o.reserved[1] = 3
+    o.reserved = 3
     assert _call(5, opts=o) == -1
     o = salo.make_options()
-    o.reserved[0] = 1
+    o.no_f16 = 2
     assert _call(5, opts=o) == -1
     o = salo.make_options()
     o.mode = 9

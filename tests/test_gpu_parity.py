@@ -79,14 +79,49 @@ def test_random_pairs_every_variant(dev, lanes, cols):
 
 @pytest.mark.parametrize("scoring", [(1, -4, 6, 1), (2, -3, 5, 2), (1, -1, 1, 1),
                                      (3, 0, 2, 1), (1, -2, 0, 1), (5, -4, 3, 0),
-                                     (1, -4, 0, 0), (200, -100, 50, 7), (7, -300, 12, 3)])
+                                     (1, -4, 0, 0), (200, -100, 50, 7), (7, -300, 12, 3),
+                                     (8, -12, 10, 2), (16, -20, 30, 5), (1, 0, 0, 0),
+                                     (2, -2048, 2046, 1)])
 def test_scorings(dev, scoring):
+    """Scorings whose values fit a binary16 row table (one byte each) run in
+    binary16 cells where the score bound allows; the others, and every
+    scoring with binary16 switched off, in 16-bit integer or 32-bit cells."""
     b = I.random_pairs(21, 400, 200)
     want = oracle_align(b, scoring)
     for lanes, cols in [(4, 16), (16, 8)]:
-        _say("random_pairs seed 21 scoring", scoring, "lanes", lanes, "cols", cols)
-        assert_same(b, gpu_align(b, scoring, mode="plain", lanes=lanes, cols=cols), want,
-                    "scoring %s" % (scoring,))
+        for no_f16 in (False, True):
+            _say("random_pairs seed 21 scoring", scoring, "lanes", lanes, "cols", cols,
+                 "no_f16", no_f16)
+            assert_same(b, gpu_align(b, scoring, mode="plain", lanes=lanes, cols=cols,
+                                     no_f16=no_f16), want,
+                        "scoring %s no_f16=%s" % (scoring, no_f16))
+    _say("random_pairs seed 21 scoring", scoring, "persistent")
+    assert_same(b, gpu_align(b, scoring), want, "scoring %s persistent" % (scoring,))
+
+
+def test_binary16_limit_edge(dev):
+    """Best scores at and just past 2048, the largest integer up to which
+    binary16 cells are exact (match * min(m, n) <= 2048 keeps a pair in
+    binary16 cells; one more base moves it to 16-bit integer cells)."""
+    rng = np.random.default_rng(78)
+    qs, ts = [], []
+    for match, mns in ((1, (2047, 2048, 2049)), (4, (511, 512, 513))):
+        for mn in mns:
+            base = rng.integers(0, 4, mn).astype(np.uint8)
+            qs.append(base)
+            ts.append(base.copy())
+            mut = base.copy()
+            mut[rng.choice(mn, 3, replace=False)] ^= 2
+            qs.append(base)
+            ts.append(np.concatenate([mut, rng.integers(0, 4, 5).astype(np.uint8)]))
+    b = I.from_codes(qs, ts, "binary16_limit")
+    for match in (1, 4):
+        sc = (match, -4, 6, 1)
+        want = oracle_align(b, sc)
+        for opts in ({"mode": "plain", "lanes": 64, "cols": 16}, {"mode": "persistent"},
+                     {"mode": "persistent", "no_f16": True}):
+            _say("binary16 limit scoring", sc, opts)
+            assert_same(b, gpu_align(b, sc, **opts), want, "binary16 limit %s %s" % (sc, opts))
 
 
 def _edge_batch():
@@ -138,6 +173,33 @@ def test_int32_forced_by_score_bound(dev):
     assert int(want[0].max()) > 32767
     _say("long_uneven 60 pairs scoring", sc)
     assert_same(b, gpu_align(b, sc), want, "int32 by bound")
+
+
+def test_packed_limit_edge(dev):
+    """Scores right at the largest 16-bit cell value (0x7BFF), where the
+    half-precision maximum still orders cells exactly, and one base past
+    it, where the pair moves to 32-bit cells.  With match=16 and
+    mismatch=-1 a pair with min(m, n) = 1982 has 16*1983+1 = 31729 <= 31743
+    (16-bit) and min(m, n) = 1983 has 31745 (32-bit)."""
+    rng = np.random.default_rng(77)
+    qs, ts = [], []
+    for mn in (1982, 1983):
+        base = rng.integers(0, 4, mn).astype(np.uint8)
+        qs.append(base)
+        ts.append(base.copy())                       # perfect match: score 16*mn
+        mut = base.copy()
+        mut[rng.choice(mn, 4, replace=False)] ^= 1   # four substitutions
+        qs.append(base)
+        ts.append(mut)
+        qs.append(base[: mn - 7])                    # query ends inside the target
+        ts.append(np.concatenate([rng.integers(0, 4, 9).astype(np.uint8), base]))
+    b = I.from_codes(qs, ts, "packed_limit")
+    sc = (16, -1, 6, 1)
+    want = oracle_align(b, sc)
+    assert int(want[0][0]) == 16 * 1982 and int(want[0][3]) == 16 * 1983
+    for mode in ("plain", "persistent"):
+        _say("packed limit edge mode", mode)
+        assert_same(b, gpu_align(b, sc, mode=mode), want, "packed limit " + mode)
 
 
 def test_invalid_pairs_are_flagged(dev):

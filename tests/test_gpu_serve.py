@@ -27,13 +27,14 @@ def test_alone_equals_mix(dev):
     sizes = S.request_sizes(40, 5, max_pairs=200)
     arrivals = S.poisson_arrivals(40, 2000.0, 5)     # arrivals much faster than service
     reqs = S.split_requests(pool, sizes, arrivals)
-    ex = S.GpuExecutor(n_streams=4)
-    budget = 3 * max(S.footprint_bytes(r.batch) for r in reqs)
+    ex = S.GpuExecutor(n_slots=2, max_pairs=1024, max_bytes=1 << 20)
+    budget = 6 * max(S.footprint_bytes(r.batch) for r in reqs)
     print("[case] serve 40 requests, budget", budget, flush=True)
     st = S.Server(ex, budget_bytes=budget).run(reqs)
     assert st.completed == 40
     assert st.max_inflight_bytes <= budget
     assert st.max_inflight >= 2
+    assert max(st.launch_sizes) >= 2          # waiting requests were merged
     for r in reqs:
         b = r.batch
         want = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets)
