@@ -129,7 +129,16 @@ def main(argv=None) -> int:
 
     gen = I.WORKLOADS[args.workload]
     t0 = time.time()
-    batch = gen(0, args.pairs) if args.pairs else gen(0)
+    kw = {}
+    if args.workload in ("short_reads", "long_uneven", "mixed"):
+        last = [time.time()]
+
+        def progress(done, total):
+            if time.time() - last[0] > 10:
+                last[0] = time.time()
+                log("generating %s: %d / %d pairs" % (args.workload, done, total))
+        kw["progress"] = progress
+    batch = gen(0, args.pairs, **kw) if args.pairs else gen(0, **kw)
     cells = batch.cells()
     log("workload %s: %d pairs, %.3e cells, generated in %.1fs" % (
         args.workload, batch.n_pairs, cells, time.time() - t0))
@@ -194,13 +203,22 @@ def main(argv=None) -> int:
     if args.compare_plain and args.mode != "plain":
         popts = dict(mode="plain", lanes=args.plain_lanes, cols=16,
                      waves_per_cu=args.waves_per_cu)
+        t_first = time.perf_counter()
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
         torch.cuda.synchronize()
+        # a plain step of many seconds reports each step (the host waits
+        # between steps, so the timed launches stay back to back only when
+        # steps are short)
+        pm_progress = time.perf_counter() - t_first > 5.0
+        log("plain warm-up step: %.1f s" % (time.perf_counter() - t_first))
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for _ in range(args.steps):
+        for k in range(args.steps):
             salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
+            if pm_progress:
+                torch.cuda.synchronize()
+                log("plain step %d done" % k)
         e1.record(stream)
         torch.cuda.synchronize()
         pm = e0.elapsed_time(e1) / args.steps

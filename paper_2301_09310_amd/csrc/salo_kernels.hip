@@ -118,22 +118,22 @@ struct BaseStream {
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
 
-// The wave's boundary-column slot behind a range-checked buffer descriptor:
-// an index outside the slot reads 0 and drops the store.
+// The wave's boundary-column slot behind a range-checked buffer descriptor
+// of kSlotBytes: a byte offset at or past the end reads 0 and drops the
+// store (the hardware checks the offset against the descriptor's size).
+// Entries are 8 bytes, (H, E), at byte offset 8 * (row * groups + group).
 struct Slot {
     uint32_t *base;   // wave-uniform
 
-    __device__ __forceinline__ uint2 load(size_t entry) const {
+    __device__ __forceinline__ uint2 load(uint32_t off) const {
         const __amdgpu_buffer_rsrc_t r =
             __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)kSlotBytes, kBufDword3);
-        const uint32_t off = entry < (size_t)(kSlotWords / 2) ? (uint32_t)entry * 8u : 0xFFFFFFF0u;
         const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
         return make_uint2(v.x, v.y);
     }
-    __device__ __forceinline__ void store(size_t entry, uint32_t h, uint32_t e) const {
+    __device__ __forceinline__ void store(uint32_t off, uint32_t h, uint32_t e) const {
         const __amdgpu_buffer_rsrc_t r =
             __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)kSlotBytes, kBufDword3);
-        const uint32_t off = entry < (size_t)(kSlotWords / 2) ? (uint32_t)entry * 8u : 0xFFFFFFF0u;
         u32x2 v;
         v.x = h;
         v.y = e;
@@ -143,10 +143,9 @@ struct Slot {
 
 // DPP move of `v` from lane-1 to every lane (wave_shr:1), with `bnd` at
 // each group's first lane (l == 0), whatever the group width.
-__device__ __forceinline__ uint32_t shift_in(uint32_t v, uint32_t bnd, int l) {
-    const uint32_t s =
-        (uint32_t)__builtin_amdgcn_update_dpp((int)bnd, (int)v, 0x138, 0xf, 0xf, false);
-    return l == 0 ? bnd : s;
+__device__ __forceinline__ uint32_t shift_in(uint32_t v, uint32_t bnd, bool first) {
+    const uint32_t s = (uint32_t)__builtin_amdgcn_mov_dpp((int)v, 0x138, 0xf, 0xf, true);
+    return first ? bnd : s;
 }
 
 __device__ __forceinline__ int wave_max(int v) {
@@ -295,6 +294,12 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
     const Slot bslot{slot};
+    // slot byte offsets: row r of this lane's group is at r * row_bytes +
+    // ld_lane; the row a lane writes at step s is s - l, hence st_lane
+    // (rows below 64 Ki and at most 64 groups keep every offset in 32 bits)
+    const uint32_t row_bytes = (uint32_t)Gs * 8u;
+    const uint32_t ld_lane = (uint32_t)gs * 8u;
+    const int32_t st_lane = (gs - l * Gs) * 8;
 
     for (int c = 0; c < C; ++c) {
         const int col0 = c * W * K + l * K;
@@ -354,13 +359,15 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 
         const bool have_bnd = c > 0;   // implies R >= 1 (C == 0 when R == 0)
         const bool write_bnd = c + 1 < C;
+        const bool first_lane = l == 0;
+        const bool last_lane = l == W - 1 && mine;
         uint2 fifo[4];
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             fifo[r] = make_uint2(0u, 0u);
             if (have_bnd) {
                 const int rr = min(r, R - 1);
-                fifo[r] = bslot.load((size_t)rr * Gs + gs);
+                fifo[r] = bslot.load(ld_lane + (uint32_t)rr * row_bytes);
             }
         }
 
@@ -395,80 +402,94 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 const uint2 bnd = fifo[j & 3];
                 if (have_bnd) {
                     const int rr = min(s + 4, R - 1);
-                    fifo[j & 3] = bslot.load((size_t)rr * Gs + gs);
+                    fifo[j & 3] = bslot.load(ld_lane + (uint32_t)rr * row_bytes);
                 }
-                const uint32_t hin = shift_in(hout, bnd.x, l);
-                const uint32_t ein = shift_in(eout, bnd.y, l);
-                if (i >= 0 && i < R) {
-                    uint32_t e = ein;
-                    uint32_t hd = hprev;
-                    uint32_t rowmax = 0;
-                    if constexpr (CT == kCellF16) {
-                        // S(i,j) = hd + table value, as binary16 numbers;
-                        // E is clamped at 0 (so H >= 0 needs no fourth
-                        // operand); F may go negative, down to -alpha
-                        const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
-                        const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
-                        const uint32_t TA = i < pr[0].n ? (MM4 ^ (XM << (bA << 3))) : 0u;
-                        const uint32_t TB = i < pr[1].n ? (MM4 ^ (XM << (bB << 3))) : 0u;
+                const uint32_t hin = shift_in(hout, bnd.x, first_lane);
+                const uint32_t ein = shift_in(eout, bnd.y, first_lane);
+                // every lane runs every step: rows outside [0, n) of a pair
+                // (the wavefront ramp, and rows past the shorter pairs of the
+                // unit) use a zero substitution table, so each of their
+                // values is bounded by a real cell of an earlier row and can
+                // never become, or tie ahead of, the first maximum
+                uint32_t e = ein;
+                uint32_t hd = hprev;
+                uint32_t rowmax = 0;
+                if constexpr (CT == kCellF16) {
+                    // S(i,j) = hd + table value, as binary16 numbers;
+                    // E is clamped at 0 (so H >= 0 needs no fourth
+                    // operand); F may go negative, down to -alpha
+                    const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
+                    const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
+                    const uint32_t TA =
+                        (uint32_t)i < (uint32_t)pr[0].n ? (MM4 ^ (XM << (bA << 3))) : 0u;
+                    const uint32_t TB =
+                        (uint32_t)i < (uint32_t)pr[1].n ? (MM4 ^ (XM << (bB << 3))) : 0u;
+                    // diagonal terms in place, last column first (each
+                    // H[k] still holds row i-1 when column k+1 reads it)
 #pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            const uint32_t T = __builtin_amdgcn_perm(TB, TA, SEL[k]);
-                            const uint32_t d = hadd(hd, T);
-                            hd = H[k];
-                            const uint32_t f = F[k];
-                            const uint32_t hh = pmax3(d, f, e);
-                            H[k] = hh;
-                            const uint32_t ha = hadd(hh, NAL2);
-                            F[k] = hmax(hadd(f, NBE2), ha);
-                            e = pmax3(hadd(e, NBE2), ha, 0u);
-                            if (k & 1)
-                                rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
-                        }
-                    } else if constexpr (CT == kCellU16) {
-                        const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
-                        const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
-                        const uint32_t TA = i < pr[0].n ? (KC << (bA << 3)) : 0u;
-                        const uint32_t TB = i < pr[1].n ? (KC << (bB << 3)) : 0u;
+                    for (int k = K - 1; k >= 0; --k)
+                        H[k] = hadd(k > 0 ? H[k - 1] : hd,
+                                    __builtin_amdgcn_perm(TB, TA, SEL[k]));
 #pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            const uint32_t T = __builtin_amdgcn_perm(TB, TA, SEL[k]);
-                            const uint32_t d = psub(padd(hd, T), NB2);
-                            hd = H[k];
-                            const uint32_t f = F[k];
-                            const uint32_t hh = pmax3(d, f, e);
-                            H[k] = hh;
-                            const uint32_t ha = psub(hh, AL2);
-                            F[k] = pmax(psub(f, BE2), ha);
-                            e = pmax(psub(e, BE2), ha);
-                            // row maximum two columns at a time
-                            if (k & 1)
-                                rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
-                        }
-                    } else {
-                        const uint32_t tb = i < pr[0].n ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
-#pragma unroll
-                        for (int k = 0; k < K; ++k) {
-                            const int sc = SEL[k] == tb ? a : b;
-                            const int d = (int)hd + sc;
-                            hd = H[k];
-                            const int f = (int)F[k];
-                            const int hh = max3i(d, f, (int)e);
-                            H[k] = (uint32_t)hh;
-                            const int ha = hh - alpha;
-                            F[k] = (uint32_t)max3i(f - beta, ha, 0);
-                            rowmax = k == 0 ? (uint32_t)hh : (uint32_t)max((int)rowmax, hh);
-                            e = (uint32_t)max3i((int)e - beta, ha, 0);
-                        }
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t f = F[k];
+                        const uint32_t hh = pmax3(H[k], f, e);
+                        H[k] = hh;
+                        const uint32_t ha = hadd(hh, NAL2);
+                        F[k] = hmax(hadd(f, NBE2), ha);
+                        e = pmax3(hadd(e, NBE2), ha, 0u);
+                        if (k & 1)
+                            rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
                     }
-                    hprev = hin;
-                    hout = H[K - 1];
-                    eout = e;
-                    // row-level tracking of the first maximum
-                    if constexpr (PK) {
-                        const uint32_t nb = pmax(cbest, rowmax);
-                        const uint32_t chg = nb ^ cbest;
-                        cbest = nb;
+                } else if constexpr (CT == kCellU16) {
+                    const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
+                    const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
+                    const uint32_t TA = (uint32_t)i < (uint32_t)pr[0].n ? (KC << (bA << 3)) : 0u;
+                    const uint32_t TB = (uint32_t)i < (uint32_t)pr[1].n ? (KC << (bB << 3)) : 0u;
+#pragma unroll
+                    for (int k = K - 1; k >= 0; --k)
+                        H[k] = psub(padd(k > 0 ? H[k - 1] : hd,
+                                         __builtin_amdgcn_perm(TB, TA, SEL[k])),
+                                    NB2);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const uint32_t f = F[k];
+                        const uint32_t hh = pmax3(H[k], f, e);
+                        H[k] = hh;
+                        const uint32_t ha = psub(hh, AL2);
+                        F[k] = pmax(psub(f, BE2), ha);
+                        e = pmax(psub(e, BE2), ha);
+                        // row maximum two columns at a time
+                        if (k & 1)
+                            rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
+                    }
+                } else {
+                    const uint32_t tb = (uint32_t)i < (uint32_t)pr[0].n
+                                            ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
+#pragma unroll
+                    for (int k = K - 1; k >= 0; --k)
+                        H[k] = (uint32_t)((int)(k > 0 ? H[k - 1] : hd) +
+                                          (SEL[k] == tb ? a : b));
+#pragma unroll
+                    for (int k = 0; k < K; ++k) {
+                        const int f = (int)F[k];
+                        const int hh = max3i((int)H[k], f, (int)e);
+                        H[k] = (uint32_t)hh;
+                        const int ha = hh - alpha;
+                        F[k] = (uint32_t)max3i(f - beta, ha, 0);
+                        rowmax = k == 0 ? (uint32_t)hh : (uint32_t)max((int)rowmax, hh);
+                        e = (uint32_t)max3i((int)e - beta, ha, 0);
+                    }
+                }
+                hprev = hin;
+                hout = H[K - 1];
+                eout = e;
+                // row-level tracking of the first maximum
+                if constexpr (PK) {
+                    const uint32_t nb = pmax(cbest, rowmax);
+                    const uint32_t chg = nb ^ cbest;
+                    cbest = nb;
+                    if (chg != 0u) {
                         if (chg & 0xFFFFu) {
                             crow[0] = i;
 #pragma unroll
@@ -483,19 +504,21 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                 *reinterpret_cast<uint4 *>(my_saved + K + k) =
                                     make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
                         }
-                    } else {
-                        if ((int)rowmax > (int)cbest) {
-                            cbest = rowmax;
-                            crow[0] = i;
-#pragma unroll
-                            for (int k = 0; k < K; k += 4)
-                                *reinterpret_cast<uint4 *>(my_saved + k) =
-                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
-                        }
                     }
-                    if (write_bnd && l == W - 1 && mine)
-                        bslot.store((size_t)i * Gs + gs, hout, eout);
+                } else {
+                    if ((int)rowmax > (int)cbest) {
+                        cbest = rowmax;
+                        crow[0] = i;
+#pragma unroll
+                        for (int k = 0; k < K; k += 4)
+                            *reinterpret_cast<uint4 *>(my_saved + k) =
+                                make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                    }
                 }
+                // the group's last lane holds row s - (W-1): a real row once
+                // s >= W-1 (and always below R, as s < R + W - 1)
+                if (write_bnd && s >= W - 1 && last_lane)
+                    bslot.store((uint32_t)(st_lane + s * (int32_t)row_bytes), hout, eout);
                 }  // s < S
             }
         }
@@ -583,10 +606,15 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     }
 }
 
+// Resident waves per SIMD each width is compiled for: 512 VGPRs per lane
+// hold three waves of at most 168 registers (K <= 16) or two of at most 256
+// (K = 32).  The host sizes the grid to match.
+template <int K> constexpr int kMinWaves = K <= 16 ? 3 : 2;
+
 // Plain mode: pairs in input order, fixed lanes/cols, units of 128/W pairs
 // dealt to waves round robin.
 template <int K>
-__global__ __launch_bounds__(64) void plain_kernel(KParams P, int W) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>, 8))) void plain_kernel(KParams P, int W) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
     BaseStream qs, ts;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
@@ -607,7 +635,7 @@ __global__ __launch_bounds__(64) void plain_kernel(KParams P, int W) {
 // width comes from the unit's bin; the query columns per lane (K) are fixed
 // per launch so every width shares one register budget.
 template <int K>
-__global__ __launch_bounds__(64) void persistent_kernel(KParams P) {
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>, 8))) void persistent_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
     BaseStream qs, ts;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);

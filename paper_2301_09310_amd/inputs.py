@@ -278,7 +278,7 @@ def plain_small(seed: int = 0, n_pairs: int = 1000) -> Batch:
     return b
 
 
-def short_reads(seed: int = 0, n_pairs: int = 2_000_000) -> Batch:
+def short_reads(seed: int = 0, n_pairs: int = 2_000_000, progress=None) -> Batch:
     """Short-read extension: source length U{50..250}; target = source plus
     a U{0..100} flank split at random into left/right; query = source with
     1% substitutions and 0.1% single-base indels; 10% of pairs are
@@ -286,6 +286,8 @@ def short_reads(seed: int = 0, n_pairs: int = 2_000_000) -> Batch:
     q_parts, t_parts = [], []
     for c0 in range(0, n_pairs, CHUNK_PAIRS):
         n = min(CHUNK_PAIRS, n_pairs - c0)
+        if progress is not None:
+            progress(c0, n_pairs)
         rng = np.random.default_rng([seed, 2, c0 // CHUNK_PAIRS])
         src_lens = rng.integers(50, 251, n).astype(np.int64)
         flank = rng.integers(0, 101, n).astype(np.int64)
@@ -310,7 +312,7 @@ def short_reads(seed: int = 0, n_pairs: int = 2_000_000) -> Batch:
     return b
 
 
-def long_uneven(seed: int = 0, n_pairs: int = 200_000) -> Batch:
+def long_uneven(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch:
     """Long uneven extension: source length round(exp(U[ln 500, ln 5000]));
     target length round(source * U[1.1, 1.5]) with the source at a random
     offset; query = source with 5% substitutions and 3% indels of geometric
@@ -318,6 +320,8 @@ def long_uneven(seed: int = 0, n_pairs: int = 200_000) -> Batch:
     q_parts, t_parts = [], []
     for c0 in range(0, n_pairs, CHUNK_PAIRS):
         n = min(CHUNK_PAIRS, n_pairs - c0)
+        if progress is not None:
+            progress(c0, n_pairs)
         rng = np.random.default_rng([seed, 3, c0 // CHUNK_PAIRS])
         src_lens = np.rint(np.exp(rng.uniform(np.log(500), np.log(5000), n))).astype(np.int64)
         tl = np.rint(src_lens * rng.uniform(1.1, 1.5, n)).astype(np.int64)
@@ -332,7 +336,7 @@ def long_uneven(seed: int = 0, n_pairs: int = 200_000) -> Batch:
     return b
 
 
-def mixed(seed: int = 0, n_pairs: int = 4_000_000) -> Batch:
+def mixed(seed: int = 0, n_pairs: int = 4_000_000, progress=None) -> Batch:
     """Batched mixed workload: source length drawn from a mixture of
     60% U{100..300}, 35% U{300..1000}, 5% U{1000..10000}; target length
     round(1.2 * source) with the source at a random offset; query = source
@@ -340,6 +344,8 @@ def mixed(seed: int = 0, n_pairs: int = 4_000_000) -> Batch:
     q_parts, t_parts = [], []
     for c0 in range(0, n_pairs, CHUNK_PAIRS):
         n = min(CHUNK_PAIRS, n_pairs - c0)
+        if progress is not None:
+            progress(c0, n_pairs)
         rng = np.random.default_rng([seed, 4, c0 // CHUNK_PAIRS])
         src_lens = mixed_lengths(rng, n)
         tl = np.rint(1.2 * src_lens).astype(np.int64)
