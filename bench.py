@@ -33,24 +33,41 @@ SCORING = (1, -4, 6, 1)
 OPS_PER_CELL = 11
 # gfx950 VALU: 256 CUs x 64 lanes x 2.4 GHz; packed 16-bit ops do 2 elements.
 PEAK_TOPS = {"u16x2": 256 * 64 * 2.4e9 * 2 / 1e12, "i32": 256 * 64 * 2.4e9 / 1e12}
+PEAK_TOPS["f16x2"] = PEAK_TOPS["f16x2+u16x2"] = PEAK_TOPS["u16x2"]   # packed 16-bit rate
+HBM_PEAK_GBS = 8000.0
+
+
+def cell_dtype(batch, scoring=SCORING) -> str:
+    """Cell arithmetic the library picks for this batch: binary16 where a
+    pair's best score is at most 2048 (the scoring fits the binary16 row
+    table), 16-bit integers elsewhere (32-bit beyond the 16-bit bound)."""
+    match, mism = scoring[0], scoring[1]
+    mn = np.minimum(batch.q_lens(), batch.t_lens())
+    half = match * mn <= 2048
+    u16 = match * (mn + 1) - mism <= 0x7BFF
+    if half.all():
+        return "f16x2"
+    if (half | u16).all():
+        return "f16x2+u16x2"
+    return "i32"
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash() -> str:
-    """sha256 of the DP kernel sources; profiler byte counts are only valid
-    for the kernel they were taken on."""
+def kernel_source_hash(files=("salo_kernels.hip", "salo_internal.h")) -> str:
+    """sha256 of a kernel's sources (the DP kernel by default); profiler
+    byte counts are only valid for the kernel they were taken on."""
     import hashlib
     h = hashlib.sha256()
-    for f in ("salo_kernels.hip", "salo_internal.h"):
+    for f in files:
         with open(os.path.join(ROOT, "paper_2301_09310_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
 
-def measured_traffic(workload: str):
+def measured_traffic(workload: str, source_hash=None):
     """HBM bytes per DP launch for this kernel source and workload, from the
     rocprofv3 FETCH_SIZE / WRITE_SIZE runs recorded in traffic.json (scaled
     by the plain-copy calibration); None when not measured for this source."""
@@ -59,7 +76,7 @@ def measured_traffic(workload: str):
         return None
     with open(path) as f:
         table = json.load(f)
-    rec = table.get(kernel_source_hash(), {}).get(workload)
+    rec = table.get(source_hash or kernel_source_hash(), {}).get(workload)
     return None if rec is None else float(rec["bytes_per_launch"])
 
 
@@ -96,6 +113,9 @@ def main(argv=None) -> int:
                     help="only run 3 device-to-device copies of BYTES bytes (a known-"
                          "traffic kernel for scaling the profiler's byte counters)")
     ap.add_argument("--plain-lanes", type=int, default=4)
+    ap.add_argument("--pack", action="store_true",
+                    help="time the on-device packing of the workload's reads written as "
+                         "characters (forward and reverse-complement)")
     args = ap.parse_args(argv)
 
     if args.gpus != 1:
@@ -126,6 +146,8 @@ def main(argv=None) -> int:
 
     if args.serve:
         return serve_bench(args)
+    if args.pack:
+        return pack_bench(args)
 
     gen = I.WORKLOADS[args.workload]
     t0 = time.time()
@@ -241,7 +263,7 @@ def main(argv=None) -> int:
     log("parity on %d sampled pairs: %s" % (k, "bit-exact" if parity_ok else "MISMATCH"))
 
     # roofline of the DP kernel: algorithmic int ops per launch / launch time
-    dtype = "u16x2"
+    dtype = cell_dtype(batch)
     kern_ms = float(np.mean(dp_ms))
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TOPS[dtype]
@@ -283,6 +305,87 @@ def main(argv=None) -> int:
     }
     print(json.dumps(rec), flush=True)
     return 0 if parity_ok else 1
+
+
+def pack_bench(args) -> int:
+    """GB/s of salo_pack_bases on the workload's reads written as characters
+    (query and target streams), forward and reverse-complemented, against
+    HBM bandwidth; bit-exact check against the packing oracle."""
+    import torch
+    from oracle import oracle as O
+    from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import salo
+    gen = I.WORKLOADS[args.workload]
+    batch = gen(0, args.pairs) if args.pairs else gen(0)
+    letters = np.frombuffer(b"ACGT", np.uint8)
+    streams = []
+    for packed, off in ((batch.q_seqs, batch.q_offsets), (batch.t_seqs, batch.t_offsets)):
+        n = int(off[-1])
+        codes = (np.unpackbits(packed[: (n + 3) // 4, None], axis=1, bitorder="little")
+                 .reshape(-1, 4, 2) @ np.array([1, 2], np.uint8)).reshape(-1)[:n]
+        streams.append((letters[codes], off))
+    n_chars = sum(c.size for c, _ in streams)
+    n_seqs = sum(o.size - 1 for _, o in streams)
+    log("pack workload %s: %d characters in 2 streams" % (args.workload, n_chars))
+    dev_streams = [(torch.from_numpy(c).cuda(), torch.from_numpy(o).cuda(),
+                    torch.empty(((c.size + 15) // 16) * 4, dtype=torch.uint8, device="cuda"))
+                   for c, o in streams]
+    stream = torch.cuda.current_stream()
+    res = {}
+    ok = True
+    for rc in (False, True):
+        for _ in range(max(args.warmup, 1)):
+            for c, o, p in dev_streams:
+                salo.pack_bases(c, o, revcomp=rc, out=p, stream=stream)
+        torch.cuda.synchronize()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            for c, o, p in dev_streams:
+                salo.pack_bases(c, o, revcomp=rc, out=p, stream=stream)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        ms = e0.elapsed_time(e1) / args.steps
+        # algorithmic bytes: characters in, packed bases out (+ offsets read
+        # by the reverse-complement kernel)
+        nbytes = n_chars + sum(p.numel() for _, _, p in dev_streams) + \
+            (8 * (n_seqs + 2) if rc else 0)
+        gbs = nbytes / (ms * 1e-3) / 1e9
+        for (c, o), (_, _, p) in zip(streams, dev_streams):
+            want, _ = O.pack(c, o, revcomp=rc)
+            ok &= np.array_equal(p.cpu().numpy(), want)
+        key = "revcomp" if rc else "forward"
+        res[key] = {"ms": round(ms, 4), "gbs": round(gbs, 1), "bytes": nbytes}
+        log("pack %s: %.3f ms per pass, %.1f GB/s" % (key, ms, gbs))
+    cpu = None
+    if not args.no_cpu_baseline:
+        c0 = time.perf_counter()
+        for c, o in streams:
+            O.pack(c, o, revcomp=False)
+        dt = time.perf_counter() - c0
+        cpu = {"value": round(res["forward"]["bytes"] / dt / 1e9, 3), "unit": "GB/s",
+               "cores": 1, "kind": "oracle",
+               "sample": "both character streams of the %s batch, forward, %.2fs" % (
+                   args.workload, dt)}
+    fwd = res["forward"]
+    pack_hash = kernel_source_hash(("salo_pack.hip",))
+    rec = {"metric": "packing GB/s (characters in + packed bases out, bit-exact vs oracle)",
+           "value": fwd["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": max(args.warmup, 1), "ms_per_step": fwd["ms"], "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "u8", "data": "synthetic",
+           "config": {"workload": args.workload + " reads as characters",
+                      "characters": n_chars, "sequences": n_seqs,
+                      "parity": "bit-exact, full streams" if ok else "MISMATCH"},
+           "roofline": {"bound": "hbm", "achieved": fwd["gbs"], "peak": HBM_PEAK_GBS,
+                        "unit": "GB/s", "frac": round(fwd["gbs"] / HBM_PEAK_GBS, 4),
+                        "traffic": measured_traffic("pack_" + args.workload, pack_hash),
+                        "traffic_unit": "bytes per pass (both streams)",
+                        "algorithmic_bytes": fwd["bytes"], "kernel": "pack_forward",
+                        "kernel_source": pack_hash},
+           "revcomp": res["revcomp"], "cpu_baseline": cpu}
+    print(json.dumps(rec), flush=True)
+    return 0 if ok else 1
 
 
 def serve_bench(args) -> int:
@@ -329,7 +432,7 @@ def serve_bench(args) -> int:
                               "max_inflight": summ["max_inflight"]}
         log("%.1fx: %s" % (f, json.dumps(runs["%.1fx" % f])))
     rec = {"metric": METRIC, "value": runs["0.8x"]["p99_ms"], "unit": "ms (p99 at 0.8x)",
-           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "u16x2",
+           "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f16x2+u16x2",
            "config": {"workload": "served mixed requests", "requests": args.serve_requests,
                       "warmup_requests": args.serve_warmup, "pairs_per_request": "U{1..4096}",
                       "pool_pairs": pool.n_pairs, "budget_gb": args.serve_budget_gb,

@@ -166,6 +166,37 @@ salo_status_t salo_set_bins(const salo_bin_t *bins, int32_t n_bins);
  * the table's length. */
 salo_status_t salo_get_bins(salo_bin_t *bins, int32_t max_bins, int32_t *n_bins);
 
+/*
+ * Pack character reads into the 2-bit stream the align calls read (reads
+ * carry one byte per base, SALoBa Section II-B; the evaluation packs them
+ * on the device for every method, Section V-A).
+ *
+ * chars: DEVICE, n_chars bytes, the concatenated sequences, 4-byte aligned.
+ *   A, C, G, T are accepted in either case; any other byte is an invalid
+ *   base, written as A (0) and counted.
+ * offsets: DEVICE int64 [n_seqs+1], 8-byte aligned, the sequences' CSR in
+ *   characters (non-decreasing, offsets[0] = 0, offsets[n_seqs] = n_chars).
+ *   Read only when revcomp = 1 (it may be NULL otherwise).
+ * revcomp: 0 = output base k is chars[k]; 1 = each sequence is reverse-
+ *   complemented in place: output base k of sequence s is the complement
+ *   (A<->T, C<->G) of chars[offsets[s] + offsets[s+1] - 1 - k].  With
+ *   revcomp a base no sequence covers (offsets breaking the rule above) is
+ *   written as A and counted.
+ * packed: DEVICE, 4-byte aligned, ceil(n_chars/16)*4 bytes, fully
+ *   overwritten (base k in byte k>>2 at bits 2*(k&3); bits past the last
+ *   base are 0).  It must not overlap chars.  The output offsets of the
+ *   sequences equal the input offsets (one base per character), so
+ *   (packed, offsets) can be passed straight to the align calls.
+ * invalid_count: DEVICE counter or NULL; the kernel adds the number of
+ *   invalid bases to it (the caller clears it).
+ * Asynchronous on `stream`; host-checkable errors (n_chars < 0, NULL or
+ * misaligned pointers, revcomp not 0/1, n_seqs < 0) return
+ * SALO_ERR_INVALID and enqueue nothing; n_chars == 0 is a no-op.
+ */
+salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
+                              int64_t n_seqs, int32_t revcomp, uint8_t *packed,
+                              unsigned long long *invalid_count, hipStream_t stream);
+
 /* Message for the last non-OK status returned on this host thread. */
 const char *salo_last_error(void);
 

@@ -24,6 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gotoh_oracle.c")
+_SRCS = [_SRC, os.path.join(_HERE, "pack_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle_gotoh.so")
 _lock = threading.Lock()
 _lib = None
@@ -32,11 +33,11 @@ _lib = None
 def build(force: bool = False) -> str:
     """Compile the oracle shared library with gcc (-O2, plain scalar C)."""
     if (not force and os.path.exists(_LIB)
-            and os.path.getmtime(_LIB) >= os.path.getmtime(_SRC)):
+            and all(os.path.getmtime(_LIB) >= os.path.getmtime(f) for f in _SRCS)):
         return _LIB
     tmp = _LIB + ".tmp%d" % os.getpid()
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-pthread",
-           "-o", tmp, _SRC]
+           "-o", tmp] + _SRCS
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB)
     return _LIB
@@ -56,6 +57,8 @@ def _load():
             lib.oracle_cell_h.argtypes = [p, i64, i64, p, i64, i64, i64, i64,
                                           i64, i64, i64, i64]
             lib.oracle_cell_h.restype = i64
+            lib.oracle_pack.argtypes = [p, i64, p, i64, ctypes.c_int, p]
+            lib.oracle_pack.restype = i64
             _lib = lib
     return _lib
 
@@ -143,3 +146,20 @@ def _pack_strings(seqs):
     for k, v in enumerate(bases):
         buf[k >> 2] |= v << (2 * (k & 3))
     return np.frombuffer(bytes(buf), dtype=np.uint8), np.array(offs, np.int64)
+
+
+def pack(chars, offsets=None, revcomp: bool = False):
+    """Oracle packing of character reads into the 2-bit stream (see the
+    header of pack_oracle.c).  chars: uint8 array; offsets: int64 CSR of the
+    sequences (needed for revcomp).  Returns (packed uint8 array of
+    ceil(n/16)*4 bytes, number of invalid bases)."""
+    lib = _load()
+    chars = np.ascontiguousarray(chars, dtype=np.uint8)
+    n = chars.size
+    if offsets is None:
+        offsets = np.array([0, n], np.int64)
+    offsets = np.ascontiguousarray(offsets, dtype=np.int64)
+    out = np.zeros(((n + 15) // 16) * 4, np.uint8)
+    bad = lib.oracle_pack(_ptr(chars) if n else None, n, _ptr(offsets), offsets.size - 1,
+                          1 if revcomp else 0, _ptr(out) if out.size else None)
+    return out, int(bad)

@@ -24,7 +24,7 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 # device code: never let the compiler form packed fp32 ops
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops"]
-SOURCES = ["salo_kernels.hip", "salo_plan.hip", "salo_host.cpp"]
+SOURCES = ["salo_kernels.hip", "salo_plan.hip", "salo_pack.hip", "salo_host.cpp"]
 
 
 def _compile(src: str, obj: str) -> None:

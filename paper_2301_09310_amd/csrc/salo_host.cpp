@@ -410,6 +410,27 @@ void salo_release(void) {
     g_ws.clear();
 }
 
+salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
+                              int64_t n_seqs, int32_t revcomp, uint8_t *packed,
+                              unsigned long long *invalid_count, hipStream_t stream) {
+    if (n_chars < 0) return fail(SALO_ERR_INVALID, "n_chars < 0");
+    if (n_seqs < 0) return fail(SALO_ERR_INVALID, "n_seqs < 0");
+    if (revcomp != 0 && revcomp != 1) return fail(SALO_ERR_INVALID, "revcomp must be 0 or 1");
+    if (n_chars == 0) return SALO_OK;
+    if (!chars || !packed || (revcomp && !offsets))
+        return fail(SALO_ERR_INVALID, "NULL pointer argument");
+    if ((reinterpret_cast<uintptr_t>(chars) & 3) || (reinterpret_cast<uintptr_t>(packed) & 3))
+        return fail(SALO_ERR_INVALID, "chars and packed must be 4-byte aligned");
+    if (revcomp && (reinterpret_cast<uintptr_t>(offsets) & 7))
+        return fail(SALO_ERR_INVALID, "offsets must be 8-byte aligned");
+    if (invalid_count && (reinterpret_cast<uintptr_t>(invalid_count) & 7))
+        return fail(SALO_ERR_INVALID, "invalid_count must be 8-byte aligned");
+    const hipError_t e = launch_pack(chars, n_chars, revcomp ? offsets : nullptr, n_seqs,
+                                     revcomp != 0, packed, invalid_count, stream);
+    if (e != hipSuccess) return hip_fail(e, "launch pack kernel");
+    return SALO_OK;
+}
+
 int32_t salo_version(void) { return SALO_VERSION; }
 
 }  // extern "C"

@@ -127,6 +127,9 @@ inline bool scoring_half_ok(int32_t match, int32_t mismatch, int32_t gap_open,
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,
                         hipStream_t stream);
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream);
+hipError_t launch_pack(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
+                       int64_t n_seqs, bool revcomp, uint8_t *packed,
+                       unsigned long long *invalid, hipStream_t stream);
 bool persistent_lanes_supported(int lanes);
 
 struct PlanBuffers {

@@ -1,0 +1,279 @@
+// Packing kernels: character reads (one byte per base) into the 2-bit
+// stream the aligner reads (A=0 C=1 G=2 T=3, base k in byte k>>2 at bits
+// 2*(k&3)), optionally reverse-complemented per sequence.
+//
+// Why on the device: read data stores a base per byte (SALoBa,
+// Section II-B), and the evaluation packs reads on the GPU for every
+// method because that step alone decided a library's lead (Section V-A).
+// Packing is a streaming pass: n bytes in, n/4 bytes out, so it is bound
+// by HBM bandwidth.
+//
+// Mapping: one thread per output 32-bit word (16 bases), 256 threads per
+// block.  Forward packing reads the word's 16 characters as four aligned
+// dwords.  Reverse-complement packing needs the sequence of every output
+// base: the block finds the sequence holding its first base by a binary
+// search over the offsets, stages the following offsets in LDS, and each
+// thread walks that window; the mirrored characters of a word are
+// contiguous (in reverse), so the reads stay within a few cache lines.
+#include "salo_internal.h"
+
+namespace salo {
+namespace {
+
+constexpr int kPackThreads = 256;
+constexpr int kWin = 512;   // sequence offsets staged per block (revcomp)
+
+// 2-bit code of a character and whether it is A, C, G or T in either case
+// (the code formula maps A/a->0, C/c->1, G/g->2, T/t->3).
+__device__ __forceinline__ uint32_t char_code(uint32_t c, bool &ok) {
+    const uint32_t l = c | 0x20u;
+    ok = l == 'a' || l == 'c' || l == 'g' || l == 't';
+    return ((c >> 1) ^ (c >> 2)) & 3u;
+}
+
+// Four characters (one per byte, byte 0 first) to four 2-bit bases in the
+// low 8 bits (byte 0 -> bits 0-1), complemented when RC, invalid
+// characters as 0; adds the number of invalid characters to `bad`.
+//   code     = ((c >> 1) ^ (c >> 2)) & 3 per byte (A/a 0, C/c 1, G/g 2, T/t 3)
+//   expected = "acgt"[code] per byte (one v_perm)
+//   a byte is valid iff (c | 0x20) == expected (exact per-byte zero test)
+template <bool RC>
+__device__ __forceinline__ uint32_t pack4(uint32_t x, uint32_t &bad) {
+    const uint32_t code = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
+    const uint32_t expect = __builtin_amdgcn_perm(0u, 0x74676361u, code);
+    const uint32_t d = (x | 0x20202020u) ^ expect;
+    const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
+    const uint32_t ok = nz ^ 0x80808080u;                  // 0x80 in valid bytes
+    bad += 4u - (uint32_t)__builtin_popcount(ok);
+    uint32_t c = RC ? (code ^ 0x03030303u) : code;
+    c &= (ok >> 6) | (ok >> 7);                            // 0x03 in valid bytes
+    return (c | (c >> 6) | (c >> 12) | (c >> 18)) & 0xFFu;
+}
+
+__device__ __forceinline__ void add_invalid(unsigned long long *invalid, uint32_t bad) {
+    // one atomic per wave
+    uint32_t v = bad;
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v += __shfl_xor(v, o, 64);
+    if ((threadIdx.x & 63) == 0 && v != 0u && invalid != nullptr)
+        atomicAdd(invalid, (unsigned long long)v);
+}
+
+template <bool V4>
+__global__ __launch_bounds__(kPackThreads) void pack_forward(const uint8_t *chars, int64_t n,
+                                                             uint32_t *out,
+                                                             unsigned long long *invalid) {
+    const int64_t w = (int64_t)blockIdx.x * kPackThreads + threadIdx.x;
+    const int64_t nw = (n + 15) >> 4;
+    uint32_t bad = 0;
+    if (w < nw) {
+        const int64_t p0 = w << 4;
+        uint32_t word = 0;
+        if (p0 + 16 <= n) {
+            uint32_t x[4];
+            if constexpr (V4) {      // chars 16-byte aligned: one 16-byte load
+                const uint4 v = *reinterpret_cast<const uint4 *>(chars + p0);
+                x[0] = v.x; x[1] = v.y; x[2] = v.z; x[3] = v.w;
+            } else {
+                const uint32_t *src = reinterpret_cast<const uint32_t *>(chars + p0);
+#pragma unroll
+                for (int d = 0; d < 4; ++d) x[d] = src[d];
+            }
+#pragma unroll
+            for (int d = 0; d < 4; ++d) word |= pack4<false>(x[d], bad) << (8 * d);
+        } else {
+            for (int k = 0; k < 16 && p0 + k < n; ++k) {
+                bool ok;
+                const uint32_t code = char_code(chars[p0 + k], ok);
+                bad += ok ? 0u : 1u;
+                word |= (ok ? code : 0u) << (2 * k);
+            }
+        }
+        out[w] = word;
+    }
+    add_invalid(invalid, bad);
+}
+
+// Largest s in [lo, hi) with off[s] <= p, or lo - 1 when off[lo] > p.
+__device__ int64_t last_le(const int64_t *off, int64_t lo, int64_t hi, int64_t p) {
+    int64_t a = lo, b = hi;   // answer in [a-1, b-1]
+    while (a < b) {
+        const int64_t mid = a + ((b - a) >> 1);
+        if (off[mid] <= p) a = mid + 1;
+        else b = mid;
+    }
+    return a - 1;
+}
+
+// The 16 characters chars[start .. start+16) as four dwords (byte j of
+// g[i] is chars[start + 4i + j]); positions outside [0, n) read as 0.
+// Whole dwords are read, so the buffer must be readable up to the next
+// multiple of 4 bytes past n.
+__device__ __forceinline__ void gather16(const uint8_t *chars, int64_t n, int64_t start,
+                                         uint32_t g[4]) {
+    const int64_t a = start >> 2;                          // floor, also for negatives
+    const uint32_t sh = (uint32_t)(start - (a << 2)) * 8u;
+    const int64_t nwords = (n + 3) >> 2;
+    const uint32_t *w32 = reinterpret_cast<const uint32_t *>(chars);
+    uint32_t x[5];
+#pragma unroll
+    for (int i = 0; i < 5; ++i) {
+        const int64_t idx = a + i;
+        x[i] = (idx >= 0 && idx < nwords) ? w32[idx] : 0u;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) g[i] = __builtin_amdgcn_alignbit(x[i + 1], x[i], sh);
+}
+
+__device__ __forceinline__ void seq_bounds(const int64_t *win, int64_t s0, const int64_t *off,
+                                           int64_t n_seqs, int64_t s, int64_t &lo,
+                                           int64_t &hi) {
+    const int64_t j = s - s0;
+    if (j >= 0 && j + 1 <= kWin) {
+        lo = win[j];
+        hi = win[j + 1];
+    } else {
+        lo = off[s];
+        hi = off[s + 1];
+    }
+    (void)n_seqs;
+}
+
+__global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *chars, int64_t n,
+                                                             const int64_t *off,
+                                                             int64_t n_seqs, uint32_t *out,
+                                                             unsigned long long *invalid) {
+    __shared__ int64_t win[kWin + 1];
+    __shared__ int64_t s_first;
+    const int64_t w0 = (int64_t)blockIdx.x * kPackThreads;
+    const int64_t nw = (n + 15) >> 4;
+    if (threadIdx.x == 0) {
+        // sequence of the block's first base (off[0..n_seqs-1] are starts)
+        const int64_t s = n_seqs > 0 ? last_le(off, 0, n_seqs, w0 << 4) : -1;
+        s_first = s < 0 ? 0 : s;
+    }
+    __syncthreads();
+    const int64_t s0 = s_first;
+    for (int t = threadIdx.x; t <= kWin; t += kPackThreads) {
+        const int64_t idx = s0 + t;
+        win[t] = idx <= n_seqs ? off[idx] : INT64_MAX;
+    }
+    __syncthreads();
+
+    const int64_t w = w0 + threadIdx.x;
+    uint32_t bad = 0;
+    if (w < nw) {
+        const int64_t p0 = w << 4;
+        uint32_t word = 0;
+        // sequence of the word's first base: window index, else the table
+        int64_t s;
+        {
+            int a = 0, b = kWin;
+            while (a < b) {
+                const int mid = (a + b) >> 1;
+                if (win[mid] <= p0) a = mid + 1;
+                else b = mid;
+            }
+            const int j = a - 1;
+            if (j >= 0 && p0 < win[j + 1]) s = s0 + j;
+            else s = n_seqs > 0 ? last_le(off, 0, n_seqs, p0) : -1;
+        }
+        bool fast = false;
+        if (s >= 0 && s < n_seqs && p0 + 16 <= n) {
+            int64_t lo, hi;
+            seq_bounds(win, s0, off, n_seqs, s, lo, hi);
+            if (lo <= p0 && p0 < hi) {
+                // output base k (p = p0 + k) of sequence s comes from
+                // chars[lo + hi - 1 - p]; the word's first kb bases lie in s
+                const int64_t kb = min<int64_t>(hi - p0, 16);
+                uint32_t g[4], h[4] = {0u, 0u, 0u, 0u};
+                const int64_t A = lo + hi - 1 - p0;
+                gather16(chars, n, A - 15, g);             // g byte 15-k = chars[A - k]
+                fast = true;
+                if (kb < 16) {
+                    // the rest must lie in sequence s + 1 (else three or
+                    // more sequences share the word: per-base path)
+                    int64_t lo2, hi2;
+                    if (s + 1 < n_seqs) {
+                        seq_bounds(win, s0, off, n_seqs, s + 1, lo2, hi2);
+                        if (lo2 == hi && hi2 - lo2 >= 16 - kb) {
+                            gather16(chars, n, lo2 + hi2 - 1 - p0 - 15, h);
+                        } else {
+                            fast = false;
+                        }
+                    } else {
+                        fast = false;
+                    }
+                }
+                if (fast) {
+                    // merged byte j (= base 15 - j): from g for j >= 16 - kb
+                    const int t = 16 - (int)kb;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) {
+                        const int r = t - 4 * i;   // first byte of dword i taken from g
+                        const uint32_t mg = r <= 0 ? 0xFFFFFFFFu
+                                                   : (r >= 4 ? 0u : (0xFFFFFFFFu << (8 * r)));
+                        g[i] = (g[i] & mg) | (h[i] & ~mg);
+                    }
+                    // base k = complement of merged byte 15 - k: bases
+                    // 4q..4q+3 are dword 3-q with its bytes reversed
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        const uint32_t rev = __builtin_amdgcn_perm(0u, g[3 - q], 0x00010203u);
+                        word |= pack4<true>(rev, bad) << (8 * q);
+                    }
+                }
+            }
+        }
+        if (!fast) {
+            // per base: tails, words spanning three or more sequences, and
+            // offsets that break the documented rule
+            word = 0;
+            int64_t sc = s;
+            for (int k = 0; k < 16; ++k) {
+                const int64_t p = p0 + k;
+                if (p >= n) break;
+                int64_t lo = 0, hi = 0;
+                if (sc >= 0 && sc < n_seqs) seq_bounds(win, s0, off, n_seqs, sc, lo, hi);
+                while (sc >= 0 && sc + 1 < n_seqs && hi <= p) {
+                    ++sc;
+                    seq_bounds(win, s0, off, n_seqs, sc, lo, hi);
+                }
+                bool ok = false;
+                uint32_t code = 0;
+                if (sc >= 0 && sc < n_seqs && lo <= p && p < hi) {
+                    const int64_t src = lo + hi - 1 - p;
+                    if (src >= 0 && src < n) code = 3u - char_code(chars[src], ok);
+                }
+                bad += ok ? 0u : 1u;
+                word |= (ok ? code : 0u) << (2 * k);
+            }
+        }
+        out[w] = word;
+    }
+    add_invalid(invalid, bad);
+}
+
+}  // namespace
+
+hipError_t launch_pack(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
+                       int64_t n_seqs, bool revcomp, uint8_t *packed,
+                       unsigned long long *invalid, hipStream_t stream) {
+    const int64_t nw = (n_chars + 15) >> 4;
+    const int64_t blocks = (nw + kPackThreads - 1) / kPackThreads;
+    if (blocks <= 0) return hipSuccess;
+    if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
+    uint32_t *out = reinterpret_cast<uint32_t *>(packed);
+    if (revcomp)
+        hipLaunchKernelGGL(pack_revcomp, dim3((uint32_t)blocks), dim3(kPackThreads), 0, stream,
+                           chars, n_chars, offsets, n_seqs, out, invalid);
+    else if ((reinterpret_cast<uintptr_t>(chars) & 15) == 0)
+        hipLaunchKernelGGL((pack_forward<true>), dim3((uint32_t)blocks), dim3(kPackThreads), 0,
+                           stream, chars, n_chars, out, invalid);
+    else
+        hipLaunchKernelGGL((pack_forward<false>), dim3((uint32_t)blocks), dim3(kPackThreads), 0,
+                           stream, chars, n_chars, out, invalid);
+    return hipGetLastError();
+}
+
+}  // namespace salo

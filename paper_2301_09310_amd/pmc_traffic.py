@@ -1,6 +1,8 @@
 """Record the DP kernel's HBM traffic from rocprofv3 counter runs.
 
 Inputs are four `*_counter_collection.csv` files written by rocprofv3:
+(the DP kernel, or with --kernel pack_forward --dispatches 2 the packing
+kernel over both character streams of one `bench.py --pack` pass)
   --fetch / --write   FETCH_SIZE and WRITE_SIZE runs of
                       `bench.py --steps 1 --warmup 0 --no-cpu-baseline`
   --cfetch / --cwrite the same counters for `bench.py --calibrate-copy BYTES`
@@ -41,11 +43,11 @@ def factor(path, counter, nbytes):
     return nbytes / (kib * 1024.0), kib
 
 
-def kernel_kib(path, counter, name):
+def kernel_kib(path, counter, name, dispatches=1):
     vals = [v for (d, k), v in per_dispatch(path, counter).items() if name in k]
-    if not vals:
-        raise SystemExit("no %s dispatch in %s" % (name, path))
-    return vals[-1]          # the last (timed) launch
+    if len(vals) < dispatches:
+        raise SystemExit("fewer than %d %s dispatches in %s" % (dispatches, name, path))
+    return sum(vals[-dispatches:])   # the last (timed) launches of one step
 
 
 def main(argv=None) -> int:
@@ -58,12 +60,14 @@ def main(argv=None) -> int:
     ap.add_argument("--kernel", default="persistent_kernel")
     ap.add_argument("--workload", default="short_reads")
     ap.add_argument("--source-hash", required=True)
+    ap.add_argument("--dispatches", type=int, default=1,
+                    help="launches of the kernel that make up one step (summed)")
     ap.add_argument("--out", default=os.path.join(HERE, "traffic.json"))
     args = ap.parse_args(argv)
     ff, fk = factor(args.cfetch, "FETCH_SIZE", args.copy_bytes)
     fw, wk = factor(args.cwrite, "WRITE_SIZE", args.copy_bytes)
-    fetch = kernel_kib(args.fetch, "FETCH_SIZE", args.kernel) * 1024.0 * ff
-    write = kernel_kib(args.write, "WRITE_SIZE", args.kernel) * 1024.0 * fw
+    fetch = kernel_kib(args.fetch, "FETCH_SIZE", args.kernel, args.dispatches) * 1024.0 * ff
+    write = kernel_kib(args.write, "WRITE_SIZE", args.kernel, args.dispatches) * 1024.0 * fw
     table = {}
     if os.path.exists(args.out):
         with open(args.out) as f:

@@ -81,6 +81,8 @@ def load(path: str | None = None):
         lib.salo_get_bins.restype = i32
         lib.salo_version.argtypes = []
         lib.salo_version.restype = i32
+        lib.salo_pack_bases.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+        lib.salo_pack_bases.restype = i32
         if path is None:
             _lib = lib
         return lib
@@ -187,6 +189,42 @@ def load_tune_table(path: str) -> None:
     with open(path) as f:
         t = json.load(f)
     set_bins([(b["m_hi"], b["packed"], b["lanes"]) for b in t["bins"]])
+
+
+def pack_bases(chars, offsets=None, revcomp: bool = False, out=None, invalid=None,
+               stream=None):
+    """Pack character reads on the GPU (salo_pack_bases).  chars: uint8
+    CUDA tensor; offsets: int64 CUDA tensor (sequence CSR, needed for
+    revcomp).  Returns the packed uint8 CUDA tensor of ceil(n/16)*4 bytes
+    (or fills `out`).  `invalid`, if given, is an int64 CUDA tensor of one
+    element to which the number of invalid bases is added."""
+    import torch
+    lib = load()
+    if not chars.is_cuda or chars.dtype != torch.uint8 or not chars.is_contiguous():
+        raise ValueError("chars must be a contiguous uint8 CUDA tensor")
+    n = chars.numel()
+    nbytes = ((n + 15) // 16) * 4
+    if out is None:
+        out = torch.empty(max(nbytes, 4), dtype=torch.uint8, device=chars.device)
+    if out.numel() < nbytes:
+        raise ValueError("out holds %d bytes, %d needed" % (out.numel(), nbytes))
+    n_seqs = 0
+    off_ptr = None
+    if offsets is not None:
+        if not offsets.is_cuda or offsets.dtype != torch.int64 or not offsets.is_contiguous():
+            raise ValueError("offsets must be a contiguous int64 CUDA tensor")
+        n_seqs = offsets.numel() - 1
+        off_ptr = offsets.data_ptr()
+    inv_ptr = None
+    if invalid is not None:
+        if not invalid.is_cuda or invalid.dtype != torch.int64:
+            raise ValueError("invalid must be an int64 CUDA tensor")
+        inv_ptr = invalid.data_ptr()
+    st = lib.salo_pack_bases(chars.data_ptr() if n else None, n, off_ptr, n_seqs,
+                             1 if revcomp else 0, out.data_ptr(), inv_ptr,
+                             _stream_handle(stream))
+    _check(lib, st)
+    return out
 
 
 def reserve(max_pairs: int, stream=None):

@@ -30,7 +30,7 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
               "salo_error_count", "salo_last_timing", "salo_set_bins", "salo_get_bins",
-              "salo_last_error", "salo_release", "salo_version"]:
+              "salo_last_error", "salo_release", "salo_version", "salo_pack_bases"]:
         assert n in names
 
 
@@ -117,3 +117,23 @@ def test_bad_bin_tables(lib, table):
     with pytest.raises(salo.SaloError):
         salo.set_bins(table)
     assert salo.get_bins() == before
+
+
+def _pack(n, chars=ADDR, off=ADDR, n_seqs=1, revcomp=0, packed=ADDR, inv=None):
+    return salo.load().salo_pack_bases(chars, n, off, n_seqs, revcomp, packed, inv, NULL)
+
+
+def test_pack_validation(lib):
+    assert _pack(0, chars=None, off=None, packed=None) == 0       # no-op
+    assert _pack(-1) == -1
+    assert _pack(16, n_seqs=-1) == -1
+    assert _pack(16, revcomp=2) == -1
+    assert "revcomp" in lib.salo_last_error().decode()
+    assert _pack(16, chars=None) == -1
+    assert _pack(16, packed=None) == -1
+    assert _pack(16, off=None, revcomp=1) == -1
+    assert _pack(16, chars=ADDR + 1) == -1
+    assert "aligned" in lib.salo_last_error().decode()
+    assert _pack(16, packed=ADDR + 2) == -1
+    assert _pack(16, off=ADDR + 4, revcomp=1) == -1
+    assert _pack(16, inv=ADDR + 4) == -1
