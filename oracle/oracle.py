@@ -24,7 +24,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gotoh_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "pack_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "pack_oracle.c"), os.path.join(_HERE, "start_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle_gotoh.so")
 _lock = threading.Lock()
 _lib = None
@@ -59,6 +59,9 @@ def _load():
             lib.oracle_cell_h.restype = i64
             lib.oracle_pack.argtypes = [p, i64, p, i64, ctypes.c_int, p]
             lib.oracle_pack.restype = i64
+            lib.oracle_start_batch.argtypes = [p, p, p, p, i64, i64, i64, i64, i64,
+                                               p, p, p, p, p]
+            lib.oracle_start_batch.restype = i64
             _lib = lib
     return _lib
 
@@ -163,3 +166,29 @@ def pack(chars, offsets=None, revcomp: bool = False):
     bad = lib.oracle_pack(_ptr(chars) if n else None, n, _ptr(offsets), offsets.size - 1,
                           1 if revcomp else 0, _ptr(out) if out.size else None)
     return out, int(bad)
+
+
+def start_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_end, t_end,
+                scoring=(1, -4, 6, 1)):
+    """Oracle start positions (see the header of start_oracle.c) of the best
+    alignments whose score and end are given (the answers of align_batch).
+    Returns (q_start, t_start) int64 arrays; raises if an anchored maximum
+    differs from the given score."""
+    lib = _load()
+    n = len(q_offsets) - 1
+    arrs = [np.ascontiguousarray(a, dtype=np.int64) for a in (score, q_end, t_end)]
+    qs = np.full(n, -1, np.int64)
+    ts = np.full(n, -1, np.int64)
+    if n == 0:
+        return qs, ts
+    q_seqs = np.ascontiguousarray(q_seqs, dtype=np.uint8)
+    t_seqs = np.ascontiguousarray(t_seqs, dtype=np.uint8)
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.int64)
+    t_offsets = np.ascontiguousarray(t_offsets, dtype=np.int64)
+    a, b, o, e = scoring
+    bad = lib.oracle_start_batch(_ptr(q_seqs), _ptr(q_offsets), _ptr(t_seqs), _ptr(t_offsets),
+                                 n, a, b, o, e, _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
+                                 _ptr(qs), _ptr(ts))
+    if bad != 0:
+        raise RuntimeError("start oracle: %d pairs whose anchored maximum is not the score" % bad)
+    return qs, ts

@@ -106,3 +106,37 @@ def first_max(H):
             if v > best:
                 best, bi, bj = v, i, j
     return best, bj, bi
+
+
+def enumerate_starts(q, t, scoring, q_end, t_end):
+    """Every (t_start, q_start) of an alignment path whose first and last
+    moves align a base pair, whose last aligned pair is (t_end, q_end), with
+    the best score such paths reach; returns (best score, set of starts).
+    Exhaustive search over paths (same move costs as enumerate_h)."""
+    a, b, o, e = scoring
+    m, n = len(q), len(t)
+    best = [None]
+    starts = set()
+    sys.setrecursionlimit(10000)
+
+    def dfs(i, j, last, score, i0, j0):
+        # (i, j): next target / query base to consume
+        if last == "M" and i - 1 == t_end and j - 1 == q_end:
+            if best[0] is None or score > best[0]:
+                best[0] = score
+                starts.clear()
+            if score == best[0]:
+                starts.add((i0, j0))
+        if i > t_end + 1 or j > q_end + 1:
+            return
+        if i < n and j < m:
+            dfs(i + 1, j + 1, "M", score + _s(t[i], q[j], a, b), i0, j0)
+        if i < n and last != "":
+            dfs(i + 1, j, "D", score - (e if last == "D" else o + e), i0, j0)
+        if j < m and last != "":
+            dfs(i, j + 1, "I", score - (e if last == "I" else o + e), i0, j0)
+
+    for i0 in range(t_end + 1):
+        for j0 in range(q_end + 1):
+            dfs(i0, j0, "", 0, i0, j0)
+    return best[0], starts

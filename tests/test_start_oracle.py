@@ -1,0 +1,193 @@
+"""Pins of the start-position oracle (CPU only).
+
+For the best alignment of a pair (score S > 0 ending at the alignment
+oracle's (q_end, t_end)), the start oracle runs the anchored recurrence
+backwards from the end cell.  It is pinned to:
+  * exhaustive enumeration of every path ending at the end cell (tiny
+    strings): the oracle's start is the largest (t_start, q_start) among
+    the optimal paths' starts;
+  * hand-derived examples (tests/golden/start_examples.txt);
+  * the substring property: the local score of q[q_start..q_end] against
+    t[t_start..t_end] is S, and no optimal alignment ends there with a
+    later start;
+and planted mistakes in copies of the oracle must fail these pins.
+"""
+import ctypes
+import os
+import random
+import subprocess
+import tempfile
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2301_09310_amd import inputs as I
+from tests import bruteforce as B
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+SRC = os.path.join(os.path.dirname(HERE), "oracle", "start_oracle.c")
+SCORINGS = [(1, -4, 6, 1), (2, -3, 1, 2), (1, -1, 0, 1), (3, -4, 2, 0), (1, -2, 1, 0)]
+
+
+def _starts(start_fn, qs, ts, sc):
+    b = I.from_strings(qs, ts)
+    r = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, sc)
+    st = start_fn(b, r, sc)
+    return r, st
+
+
+def _oracle_fn(b, r, sc):
+    return O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *r, scoring=sc)
+
+
+def _tiny_cases(seed, count):
+    rng = random.Random(seed)
+    out = []
+    for _ in range(count):
+        alph = "ACGT"[: rng.choice([2, 4])]
+        q = "".join(rng.choice(alph) for _ in range(rng.randint(1, 5)))
+        t = "".join(rng.choice(alph) for _ in range(rng.randint(1, 5)))
+        out.append((q, t))
+    return out
+
+
+def _check_bruteforce(start_fn, seed=0, count=40):
+    for sc in SCORINGS:
+        cases = _tiny_cases(seed + sc[0] * 7 + sc[2], count)
+        qs, ts = [c[0] for c in cases], [c[1] for c in cases]
+        r, (qst, tst) = _starts(start_fn, qs, ts, sc)
+        for k, (q, t) in enumerate(cases):
+            s, qe, te = (int(x[k]) for x in r)
+            if s == 0:
+                if qst[k] != -1 or tst[k] != -1:
+                    return False
+                continue
+            best, starts = B.enumerate_starts(q, t, sc, qe, te)
+            if best != s:
+                return False
+            want = max(starts)          # largest t_start, then largest q_start
+            if (int(tst[k]), int(qst[k])) != want:
+                return False
+    return True
+
+
+def test_bruteforce_enumeration():
+    assert _check_bruteforce(_oracle_fn)
+
+
+def _golden():
+    rows = []
+    for line in open(os.path.join(HERE, "golden", "start_examples.txt")):
+        line = line.strip()
+        if line and not line.startswith("#"):
+            f = [x.strip() for x in line.split("|")]
+            rows.append((f[0], f[1], *[int(x) for x in f[2:]]))
+    return rows
+
+
+@pytest.mark.parametrize("row", _golden(), ids=lambda r: r[0] + "/" + r[1])
+def test_golden_examples(row):
+    q, t, s, qe, te, qs, ts = row
+    r, (qst, tst) = _starts(_oracle_fn, [q], [t], (1, -4, 6, 1))
+    assert (int(r[0][0]), int(r[1][0]), int(r[2][0])) == (s, qe, te)
+    assert (int(qst[0]), int(tst[0])) == (qs, ts)
+
+
+def test_substring_has_the_score():
+    for sc in SCORINGS[:3]:
+        b = I.random_pairs(7 + sc[0], 60, 80)
+        r = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, sc)
+        qst, tst = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *r, scoring=sc)
+        subs_q, subs_t, keep = [], [], []
+        for p in range(b.n_pairs):
+            if r[0][p] <= 0:
+                continue
+            q, t = b.pair_strings(p)
+            subs_q.append(q[qst[p]: r[1][p] + 1])
+            subs_t.append(t[tst[p]: r[2][p] + 1])
+            keep.append(p)
+        sb = I.from_strings(subs_q, subs_t)
+        rs = O.align_batch(sb.q_seqs, sb.q_offsets, sb.t_seqs, sb.t_offsets, sc)
+        assert np.array_equal(rs[0], r[0][keep])
+
+
+def test_equals_local_alignment_of_reversed_prefixes():
+    """Because (q_end, t_end) is the first maximum of the whole table, every
+    alignment scoring S inside the prefix rectangle ends at that cell.  So
+    the plain local recurrence over the reversed prefixes (the alignment
+    oracle on reversed strings) reaches S exactly at the optimal starts, and
+    its first maximum is the start oracle's answer.  This is the route the
+    GPU pass takes; here it pins the anchored oracle to the alignment
+    oracle."""
+    for sc in SCORINGS:
+        b = I.random_pairs(31 + sc[1], 150, 120)
+        r = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, sc)
+        qst, tst = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *r, scoring=sc)
+        rq, rt, keep = [], [], []
+        for p in range(b.n_pairs):
+            if r[0][p] > 0:
+                q, t = b.pair_strings(p)
+                rq.append(q[: r[1][p] + 1][::-1])
+                rt.append(t[: r[2][p] + 1][::-1])
+                keep.append(p)
+        rb = I.from_strings(rq, rt)
+        rr = O.align_batch(rb.q_seqs, rb.q_offsets, rb.t_seqs, rb.t_offsets, sc)
+        assert np.array_equal(rr[0], r[0][keep])
+        assert np.array_equal(r[1][keep] - rr[1], qst[keep])
+        assert np.array_equal(r[2][keep] - rr[2], tst[keep])
+
+
+# Note: dropping the anchor, or restoring the 0 floor, gives the same
+# answers (see the test above), so neither is a mistake to plant.
+MUTANTS = {
+    "last_max": ("if (a > best) { best = a;", "if (a >= best) { best = a;"),
+    "mirror_off_by_one": ("t_off[p] + te - i", "t_off[p] + te - i - 1"),
+    "alpha_is_extend": ("const int64_t alpha = gap_open + gap_extend,", "const int64_t alpha = gap_extend,"),
+    "start_not_mirrored": ("out_qstart[p] = qe - bj;", "out_qstart[p] = bj;"),
+}
+
+
+def _mutant_fn(path):
+    lib = ctypes.CDLL(path)
+    p, i64 = ctypes.c_void_p, ctypes.c_int64
+    lib.oracle_start_batch.argtypes = [p, p, p, p, i64, i64, i64, i64, i64, p, p, p, p, p]
+    lib.oracle_start_batch.restype = i64
+
+    def fn(b, r, sc):
+        n = b.n_pairs
+        arrs = [np.ascontiguousarray(x, np.int64) for x in r]
+        qs = np.full(n, -1, np.int64)
+        ts = np.full(n, -1, np.int64)
+        lib.oracle_start_batch(b.q_seqs.ctypes.data, b.q_offsets.ctypes.data,
+                               b.t_seqs.ctypes.data, b.t_offsets.ctypes.data, n, *sc,
+                               arrs[0].ctypes.data, arrs[1].ctypes.data, arrs[2].ctypes.data,
+                               qs.ctypes.data, ts.ctypes.data)
+        return qs, ts
+    return fn
+
+
+def _passes(fn):
+    if not _check_bruteforce(fn, seed=3, count=25):
+        return False
+    for q, t, s, qe, te, qs, ts in _golden():
+        _, (qst, tst) = _starts(fn, [q], [t], (1, -4, 6, 1))
+        if (int(qst[0]), int(tst[0])) != (qs, ts):
+            return False
+    return True
+
+
+@pytest.mark.parametrize("name", sorted(MUTANTS))
+def test_planted_mistake_is_caught(name):
+    src = open(SRC).read()
+    old, new = MUTANTS[name]
+    assert src.count(old) == 1, "mutation site moved: %s" % name
+    with tempfile.TemporaryDirectory() as tmp:
+        for tag, text in (("real", src), (name, src.replace(old, new))):
+            c = os.path.join(tmp, tag + ".c")
+            so = os.path.join(tmp, tag + ".so")
+            open(c, "w").write(text)
+            subprocess.run(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", so, c],
+                           check=True)
+        assert _passes(_mutant_fn(os.path.join(tmp, "real.so")))
+        assert not _passes(_mutant_fn(os.path.join(tmp, name + ".so")))
