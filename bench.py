@@ -113,6 +113,8 @@ def main(argv=None) -> int:
                     help="only run 3 device-to-device copies of BYTES bytes (a known-"
                          "traffic kernel for scaling the profiler's byte counters)")
     ap.add_argument("--plain-lanes", type=int, default=4)
+    ap.add_argument("--starts", action="store_true",
+                    help="also time the start-position pass on the timed step's answers")
     ap.add_argument("--pack", action="store_true",
                     help="time the on-device packing of the workload's reads written as "
                          "characters (forward and reverse-complement)")
@@ -252,6 +254,45 @@ def main(argv=None) -> int:
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
         torch.cuda.synchronize()
 
+    starts = None
+    if args.starts:
+        ans = tuple(x.clone() for x in out)
+        sq = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(2))
+        for _ in range(max(args.warmup, 1)):
+            salo.align_starts(q, qo, t, to, ans, SCORING, out=sq, stream=stream, **opts)
+        torch.cuda.synchronize()
+        s_plan, s_dp = [], []
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            salo.align_starts(q, qo, t, to, ans, SCORING, out=sq, stream=stream, timing=True,
+                              **opts)
+            pm_, dm_ = salo.last_timing(stream)
+            s_plan.append(pm_)
+            s_dp.append(dm_)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        s_ms = e0.elapsed_time(e1) / args.steps
+        a_np = [x.cpu().numpy().astype(np.int64) for x in ans]
+        s_cells = int(((a_np[1] + 1) * (a_np[2] + 1) * (a_np[0] > 0)).sum())
+        rng_s = np.random.default_rng(4)
+        k_s = min(args.parity_sample, n)
+        idx_s = np.sort(rng_s.choice(n, size=k_s, replace=False))
+        sub_s = batch.subset(idx_s)
+        w_ans = O.align_batch(sub_s.q_seqs, sub_s.q_offsets, sub_s.t_seqs, sub_s.t_offsets,
+                              SCORING)
+        w_st = O.start_batch(sub_s.q_seqs, sub_s.q_offsets, sub_s.t_seqs, sub_s.t_offsets,
+                             *w_ans, scoring=SCORING)
+        ok_s = all(np.array_equal(g.cpu().numpy()[idx_s].astype(np.int64), w)
+                   for g, w in zip(sq, w_st))
+        starts = {"ms_per_step": round(s_ms, 4), "dp_ms": round(float(np.mean(s_dp)), 4),
+                  "plan_ms": round(float(np.mean(s_plan)), 4), "cells": s_cells,
+                  "gcups": round(s_cells / (s_ms * 1e-3) / 1e9, 2),
+                  "parity": "bit-exact on %d sampled pairs" % k_s if ok_s else "MISMATCH"}
+        log("start pass: %.3f ms per step (DP %.3f), %.1f GCUPS over the reversed prefixes, %s"
+            % (s_ms, starts["dp_ms"], starts["gcups"], starts["parity"]))
+
     # parity on a sample of pairs (the full-size check lives in the tests)
     rng = np.random.default_rng(1)
     k = min(args.parity_sample, n)
@@ -302,9 +343,10 @@ def main(argv=None) -> int:
         "roofline": roof,
         "cpu_baseline": cpu,
         "comparison": comparison,
+        "starts": starts,
     }
     print(json.dumps(rec), flush=True)
-    return 0 if parity_ok else 1
+    return 0 if parity_ok and (starts is None or starts["parity"] != "MISMATCH") else 1
 
 
 def pack_bench(args) -> int:

@@ -138,6 +138,33 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
                                   int32_t *out_tend, hipStream_t stream,
                                   const salo_options_t *opts);
 
+/*
+ * Start positions of the answers of a previous align call: where the
+ * optimal path to the highest cell (Section II-A) begins.  For every pair
+ * with score > 0 ending at (q_end, t_end), out_qstart / out_tstart receive
+ * the first aligned pair of an optimal alignment ending there; among
+ * several optimal starts, the one with the largest t_start, then the
+ * largest q_start.  Computed as the first maximum of Eq. 1 over the
+ * reversed prefixes q[q_end..0], t[t_end..0] (it equals the score exactly
+ * at the optimal starts, because (q_end, t_end) is the first maximum of the
+ * whole table).
+ * Arguments: the align call's sequences, offsets, n_pairs and scoring; its
+ * three outputs score, q_end, t_end (DEVICE int32 [n_pairs], 4-byte
+ * aligned); out_qstart, out_tstart (DEVICE int32 [n_pairs], fully
+ * overwritten; -1 for pairs with score 0).  A pair whose given answer is
+ * not Eq. 1's (its reversed prefixes' best score differs, or the end lies
+ * outside the pair) gets -1 in both and is counted (salo_error_count).
+ * Runs the persistent mode (opts->mode = SALO_MODE_PLAIN returns
+ * SALO_ERR_UNSUPPORTED); other options and all errors as
+ * salo_align_batch_ex.
+ */
+salo_status_t salo_align_starts(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                const uint8_t *t_seqs, const int64_t *t_offsets,
+                                int64_t n_pairs, salo_scoring_t scoring, const int32_t *score,
+                                const int32_t *q_end, const int32_t *t_end,
+                                int32_t *out_qstart, int32_t *out_tstart, hipStream_t stream,
+                                const salo_options_t *opts);
+
 /* Pre-size the workspace of (current device, stream) for batches of up to
  * max_pairs pairs, so later calls allocate nothing (needed before graph
  * capture).  Synchronous with respect to the host. */

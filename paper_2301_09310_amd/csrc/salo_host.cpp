@@ -190,21 +190,18 @@ salo_status_t validate(const uint8_t *q_seqs, const int64_t *q_offsets, const ui
     return SALO_OK;
 }
 
-}  // namespace
-}  // namespace salo
+// Shared by the forward and the start pass: option checks, workspace,
+// KParams, then the plain or the persistent launch.  `starts` carries the
+// forward answers for the start pass (nullptr for the forward pass).
+struct StartArgs {
+    const int32_t *score, *qend, *tend;
+};
 
-using namespace salo;
-
-extern "C" {
-
-salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offsets,
-                                  const uint8_t *t_seqs, const int64_t *t_offsets,
-                                  int64_t n_pairs, salo_scoring_t scoring,
-                                  int32_t *out_score, int32_t *out_qend, int32_t *out_tend,
-                                  hipStream_t stream, const salo_options_t *opts) {
-    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
-                                out_score, out_qend, out_tend);
-    if (st != SALO_OK) return st;
+salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
+                        const uint8_t *t_seqs, const int64_t *t_offsets, int64_t n_pairs,
+                        salo_scoring_t scoring, int32_t *out_score, int32_t *out_qend,
+                        int32_t *out_tend, hipStream_t stream, const salo_options_t *opts,
+                        const StartArgs *starts) {
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
@@ -214,10 +211,12 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
         return fail(SALO_ERR_INVALID, "unknown mode");
     if (o.waves_per_cu < 0 || o.waves_per_cu > 32)
         return fail(SALO_ERR_INVALID, "waves_per_cu must be in [0, 32]");
+    if (starts && o.mode == SALO_MODE_PLAIN)
+        return fail(SALO_ERR_UNSUPPORTED, "the start pass runs in persistent mode only");
     if (n_pairs == 0) return SALO_OK;
 
     Workspace *ws = nullptr;
-    st = get_workspace(stream, &ws);
+    salo_status_t st = get_workspace(stream, &ws);
     if (st != SALO_OK) return st;
 
     // resident waves per CU at the kernel's register budget: 3 per SIMD for
@@ -235,6 +234,9 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
     p.match = scoring.match; p.mismatch = scoring.mismatch;
     p.gap_open = scoring.gap_open; p.gap_extend = scoring.gap_extend;
     p.out_score = out_score; p.out_qend = out_qend; p.out_tend = out_tend;
+    if (starts) {
+        p.in_score = starts->score; p.in_qend = starts->qend; p.in_tend = starts->tend;
+    }
     p.order = nullptr;
     p.scratch = ws->slab;
     p.errors = ws->errors;
@@ -292,6 +294,44 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
     e = launch_persistent(p, cols, (int)grid, stream);
     if (e != hipSuccess) return hip_fail(e, "launch persistent kernel");
     return mark(2);
+}
+
+}  // namespace
+}  // namespace salo
+
+using namespace salo;
+
+extern "C" {
+
+salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                  const uint8_t *t_seqs, const int64_t *t_offsets,
+                                  int64_t n_pairs, salo_scoring_t scoring,
+                                  int32_t *out_score, int32_t *out_qend, int32_t *out_tend,
+                                  hipStream_t stream, const salo_options_t *opts) {
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                out_score, out_qend, out_tend);
+    if (st != SALO_OK) return st;
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
+                     out_qend, out_tend, stream, opts, nullptr);
+}
+
+salo_status_t salo_align_starts(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                const uint8_t *t_seqs, const int64_t *t_offsets,
+                                int64_t n_pairs, salo_scoring_t scoring, const int32_t *score,
+                                const int32_t *q_end, const int32_t *t_end,
+                                int32_t *out_qstart, int32_t *out_tstart, hipStream_t stream,
+                                const salo_options_t *opts) {
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                out_qstart, out_qstart, out_tstart);
+    if (st != SALO_OK) return st;
+    if (n_pairs > 0 && (!score || !q_end || !t_end))
+        return fail(SALO_ERR_INVALID, "NULL pointer argument");
+    if ((reinterpret_cast<uintptr_t>(score) | reinterpret_cast<uintptr_t>(q_end) |
+         reinterpret_cast<uintptr_t>(t_end)) & 3)
+        return fail(SALO_ERR_INVALID, "score / q_end / t_end must be 4-byte aligned");
+    const StartArgs sa{score, q_end, t_end};
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, nullptr,
+                     out_qstart, out_tstart, stream, opts, &sa);
 }
 
 salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,

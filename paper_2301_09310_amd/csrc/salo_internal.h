@@ -67,6 +67,12 @@ struct KParams {
     const int32_t *order;          // processing order of pair ids (nullptr: identity)
     uint32_t *scratch;             // kSlotWords words per slot, one slot per block
     unsigned long long *errors;    // invalid-pair counter
+    // start-position pass: the forward answers (score, q_end, t_end) of each
+    // pair; the pass aligns the reversed prefixes ending there and writes
+    // q_start / t_start to out_qend / out_tend (nullptr: the forward pass)
+    const int32_t *in_score;
+    const int32_t *in_qend;
+    const int32_t *in_tend;
     int32_t force_int32;
     int32_t packed_ok;             // scoring admits 16-bit packed cells
     int32_t half_ok;               // scoring admits binary16 cells (and no_f16 is off)

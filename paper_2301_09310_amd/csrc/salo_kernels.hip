@@ -173,6 +173,11 @@ struct PairRef {
 
 // The pair at position `pos` of the processing order, or an absent pair
 // (no output, m = n = 0) when pos is outside [0, pos_end).
+// REV (start pass): the pair's reversed prefixes ending at its forward
+// answer (q_end, t_end): m = q_end + 1, n = t_end + 1, and q0 / t0 are the
+// stream positions of the reversed sequences' first bases (q_end, t_end);
+// a pair with forward score 0 is empty.
+template <bool REV>
 __device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, int64_t pos_end,
                                              bool present) {
     PairRef r{0, 0, 0, 0, -1, false};
@@ -187,8 +192,24 @@ __device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, int6
         r.invalid = true;
         return r;
     }
-    r.q0 = q0; r.t0 = t0; r.m = (int32_t)m; r.n = (int32_t)n;
+    if constexpr (REV) {
+        const int32_t sc = P.in_score[p], qe = P.in_qend[p], te = P.in_tend[p];
+        if (sc <= 0) return r;
+        if (qe < 0 || qe >= m || te < 0 || te >= n) {
+            r.invalid = true;
+            return r;
+        }
+        r.q0 = q0 + qe; r.t0 = t0 + te; r.m = qe + 1; r.n = te + 1;
+    } else {
+        r.q0 = q0; r.t0 = t0; r.m = (int32_t)m; r.n = (int32_t)n;
+    }
     return r;
+}
+
+// Reverse the order of the sixteen 2-bit bases of a word.
+__device__ __forceinline__ uint32_t rev2(uint32_t x) {
+    const uint32_t r = __builtin_bitreverse32(x);      // bases reversed, bit pairs swapped
+    return ((r >> 1) & 0x55555555u) | ((r & 0x55555555u) << 1);
 }
 
 struct Best {
@@ -205,8 +226,28 @@ struct Best {
     }
 };
 
+// Forward pass: score and end.  Start pass (REV): the reversed prefixes'
+// best cell (j', i') must score the forward answer; q_start = q_end - j',
+// t_start = t_end - i' go to out_qend / out_tend (a pair whose reversed
+// maximum differs from the given score, or whose end lies outside it, is
+// counted as invalid and gets -1).
+template <bool REV>
 __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr, uint64_t key) {
     if (pr.id < 0) return;
+    if constexpr (REV) {
+        const int32_t s = (int32_t)(key >> 32);
+        const int32_t want = P.in_score[pr.id];
+        if (pr.invalid || (want > 0 && s != want)) {
+            P.out_qend[pr.id] = -1; P.out_tend[pr.id] = -1;
+            atomicAdd(P.errors, 1ull);
+            return;
+        }
+        const int32_t jr = (int32_t)(0xFFFFu - (uint32_t)(key & 0xFFFF));
+        const int32_t ir = (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF));
+        P.out_qend[pr.id] = s > 0 ? (pr.m - 1) - jr : -1;
+        P.out_tend[pr.id] = s > 0 ? (pr.n - 1) - ir : -1;
+        return;
+    }
     if (pr.invalid) {
         P.out_score[pr.id] = -1; P.out_qend[pr.id] = -1; P.out_tend[pr.id] = -1;
         atomicAdd(P.errors, 1ull);
@@ -227,7 +268,7 @@ enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
 // pos0: first position (in processing order) of the unit's pairs.
 // [g0, g0 + gn): the groups processed in this pass (all G normally; fewer
 // when the unit's boundary columns do not fit one slot together).
-template <int K, int CT>
+template <int K, int CT, bool REV>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
                          uint32_t *slot, uint32_t *lds_saved) {
@@ -243,7 +284,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     PairRef pr[NPG];
 #pragma unroll
     for (int h = 0; h < NPG; ++h)
-        pr[h] = load_pair(P, pos0 + (int64_t)g * NPG + h, pos_end, mine);
+        pr[h] = load_pair<REV>(P, pos0 + (int64_t)g * NPG + h, pos_end, mine);
 
     int rmax = 0, mmax = 0;
 #pragma unroll
@@ -287,7 +328,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     uint32_t tsh[NPG];
 #pragma unroll
     for (int h = 0; h < NPG; ++h) {
-        const int64_t p0 = pr[h].t0 - l;
+        // forward: lane l reads row s - l at base t0 + s - l, 16 rows per
+        // word starting at t0 - l; REV: base t0 - (s - l), so each 16-row
+        // word is the 16 bases ending at t0 + l - s0, reversed, and the
+        // word index steps down
+        const int64_t p0 = REV ? pr[h].t0 + l - 15 : pr[h].t0 - l;
         twi[h] = p0 >> 4;                    // floor for negatives
         tsh[h] = (uint32_t)(p0 & 15) * 2u;
     }
@@ -311,7 +356,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             uint32_t qw[NPG][NQW];
 #pragma unroll
             for (int h = 0; h < NPG; ++h) {
-                const int64_t p0 = pr[h].q0 + col0;
+                // REV: column col0 + k is base q0 - col0 - k, so read the
+                // 16*NQW bases ending at q0 - col0 and reverse them
+                const int64_t p0 = REV ? pr[h].q0 - col0 - (16 * NQW - 1) : pr[h].q0 + col0;
                 const uint32_t sh = (uint32_t)(p0 & 15) * 2u;
                 uint32_t prev = qs.word(p0 >> 4);
 #pragma unroll
@@ -319,6 +366,15 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     const uint32_t next = qs.word((p0 >> 4) + 1 + w);
                     qw[h][w] = __builtin_amdgcn_alignbit(next, prev, sh);
                     prev = next;
+                }
+                if constexpr (REV) {
+                    if constexpr (NQW == 1) {
+                        qw[h][0] = rev2(qw[h][0]);
+                    } else {
+                        const uint32_t w0 = qw[h][0];
+                        qw[h][0] = rev2(qw[h][1]);
+                        qw[h][1] = rev2(w0);
+                    }
                 }
             }
 #pragma unroll
@@ -388,7 +444,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
                 for (int h = 0; h < NPG; ++h) {
                     tw[h] = __builtin_amdgcn_alignbit(tw_hi[h], tw_lo[h], tsh[h]);
-                    const int64_t wi = twi[h] + ((s0 + 16) >> 4);
+                    if constexpr (REV) tw[h] = rev2(tw[h]);
+                    const int64_t wi = REV ? twi[h] - ((s0 + 16) >> 4) : twi[h] + ((s0 + 16) >> 4);
                     tw_lo[h] = ts.word(wi);
                     tw_hi[h] = ts.word(wi + 1);
                 }
@@ -548,17 +605,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
     for (int h = 0; h < NPG; ++h) {
         const uint64_t key = group_max_u64(best[h].key(), W);
-        if (l == 0 && mine) write_result(P, pr[h], key);
+        if (l == 0 && mine) write_result<REV>(P, pr[h], key);
     }
 }
 
 // The narrowest cell type every pair of the unit admits.
+template <bool REV>
 __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, int npairs) {
     if (!P.packed_ok || P.force_int32) return kCellWide;
     const int lane = threadIdx.x & (kWave - 1);
     bool ok16 = true, okh = P.half_ok != 0;
     for (int k = lane; k < npairs; k += kWave) {
-        const PairRef r = load_pair(P, pos0 + k, pos0 + npairs, true);
+        const PairRef r = load_pair<REV>(P, pos0 + k, pos0 + npairs, true);
         if (r.id >= 0 && !r.invalid) {
             const int64_t mn = min(r.m, r.n);
             if (!packed_bound_ok(P.match, P.mismatch, mn)) ok16 = false;
@@ -570,7 +628,7 @@ __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, in
     return __builtin_amdgcn_readfirstlane(all16 ? (allh ? kCellF16 : kCellU16) : kCellWide);
 }
 
-template <int K>
+template <int K, bool REV>
 __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                              int64_t pos0, int npairs, int W, uint32_t *slot,
                                              uint32_t *lds) {
@@ -579,7 +637,7 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     int rmax = 0;
     const int lane = threadIdx.x & (kWave - 1);
     for (int k = lane; k < npairs; k += kWave) {
-        const PairRef r = load_pair(P, pos0 + k, pos0 + npairs, true);
+        const PairRef r = load_pair<REV>(P, pos0 + k, pos0 + npairs, true);
         rmax = max(rmax, r.n);
     }
     const int R = wave_max(rmax);
@@ -588,19 +646,19 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     // instantiation keeps run_unit inlined.
     const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(R, 1)));
     const int passes = (G + fit - 1) / fit;
-    const int ct = unit_cell_type(P, pos0, npairs);
+    const int ct = unit_cell_type<REV>(P, pos0, npairs);
     if (ct == kCellF16) {
         for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, kCellF16>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
+            run_unit<K, kCellF16, REV>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
                                   min(fit, G - ps * fit), W, slot, lds);
     } else if (ct == kCellU16) {
         for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, kCellU16>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
+            run_unit<K, kCellU16, REV>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
                                   min(fit, G - ps * fit), W, slot, lds);
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;
-            run_unit<K, kCellWide>(P, qs, ts, pos0 + (int64_t)half * G, pos0 + npairs,
+            run_unit<K, kCellWide, REV>(P, qs, ts, pos0 + (int64_t)half * G, pos0 + npairs,
                                    ps * fit, min(fit, G - ps * fit), W, slot, lds);
         }
     }
@@ -625,7 +683,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pos0 = u * ppu;
         const int np = (int)min<int64_t>(ppu, P.n_pairs - pos0);
-        process_unit<K>(P, qs, ts, pos0, np, W, slot, lds_saved);
+        process_unit<K, false>(P, qs, ts, pos0, np, W, slot, lds_saved);
     }
 }
 
@@ -633,8 +691,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>
 // near-equal pairs of one length bin, in descending cost order) from an
 // atomic counter until the planned units are exhausted.  The lane-group
 // width comes from the unit's bin; the query columns per lane (K) are fixed
-// per launch so every width shares one register budget.
-template <int K>
+// per launch so every width shares one register budget.  REV is the start
+// pass (reversed prefixes ending at the forward answers).
+template <int K, bool REV>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>, 8))) void persistent_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
     BaseStream qs, ts;
@@ -661,7 +720,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>
         const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
         const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
-        process_unit<K>(P, qs, ts, pos0, np, lanes, slot, lds_saved);
+        process_unit<K, REV>(P, qs, ts, pos0, np, lanes, slot, lds_saved);
     }
 }
 
@@ -691,14 +750,25 @@ bool persistent_lanes_supported(int lanes) {
 }
 
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream) {
-    if (cols == 32)
-        hipLaunchKernelGGL((persistent_kernel<32>), dim3(grid), dim3(kWave), 0, stream, p);
-    else if (cols == 16)
-        hipLaunchKernelGGL((persistent_kernel<16>), dim3(grid), dim3(kWave), 0, stream, p);
-    else if (cols == 8)
-        hipLaunchKernelGGL((persistent_kernel<8>), dim3(grid), dim3(kWave), 0, stream, p);
-    else
-        return hipErrorInvalidValue;
+    if (p.in_score) {
+        if (cols == 32)
+            hipLaunchKernelGGL((persistent_kernel<32, true>), dim3(grid), dim3(kWave), 0, stream, p);
+        else if (cols == 16)
+            hipLaunchKernelGGL((persistent_kernel<16, true>), dim3(grid), dim3(kWave), 0, stream, p);
+        else if (cols == 8)
+            hipLaunchKernelGGL((persistent_kernel<8, true>), dim3(grid), dim3(kWave), 0, stream, p);
+        else
+            return hipErrorInvalidValue;
+    } else {
+        if (cols == 32)
+            hipLaunchKernelGGL((persistent_kernel<32, false>), dim3(grid), dim3(kWave), 0, stream, p);
+        else if (cols == 16)
+            hipLaunchKernelGGL((persistent_kernel<16, false>), dim3(grid), dim3(kWave), 0, stream, p);
+        else if (cols == 8)
+            hipLaunchKernelGGL((persistent_kernel<8, false>), dim3(grid), dim3(kWave), 0, stream, p);
+        else
+            return hipErrorInvalidValue;
+    }
     return hipGetLastError();
 }
 

@@ -37,7 +37,14 @@ __device__ __forceinline__ PairLen pair_len(const KParams &P, int64_t p) {
     const int64_t n = P.t_off[p + 1] - t0;
     const bool valid = m >= 0 && n >= 0 && m <= SALO_MAX_LEN_DEV && n <= SALO_MAX_LEN_DEV &&
                        q0 >= 0 && t0 >= 0;
-    return {valid ? m : 0, valid ? n : 0};
+    if (!valid) return {0, 0};
+    if (P.in_score) {
+        // start pass: the reversed prefixes ending at the forward answer
+        const int32_t sc = P.in_score[p], qe = P.in_qend[p], te = P.in_tend[p];
+        if (sc <= 0 || qe < 0 || qe >= m || te < 0 || te >= n) return {0, 0};
+        return {(int64_t)qe + 1, (int64_t)te + 1};
+    }
+    return {m, n};
 }
 
 __device__ __forceinline__ bool pair_packed(const KParams &P, int64_t m, int64_t n) {

@@ -81,6 +81,9 @@ def load(path: str | None = None):
         lib.salo_get_bins.restype = i32
         lib.salo_version.argtypes = []
         lib.salo_version.restype = i32
+        lib.salo_align_starts.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp,
+                                          vp, ctypes.POINTER(Options)]
+        lib.salo_align_starts.restype = i32
         lib.salo_pack_bases.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
         lib.salo_pack_bases.restype = i32
         if path is None:
@@ -141,6 +144,31 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
                                  t_offsets.data_ptr(), n, sc, out[0].data_ptr(),
                                  out[1].data_ptr(), out[2].data_ptr(),
                                  _stream_handle(stream), ctypes.byref(opts))
+    _check(lib, st)
+    return out
+
+
+def align_starts(q_seqs, q_offsets, t_seqs, t_offsets, answers, scoring=(1, -4, 6, 1),
+                 out=None, stream=None, **options):
+    """Start positions of the align call's answers (salo_align_starts).
+    answers: the (score, q_end, t_end) int32 CUDA tensors of align_batch on
+    the same inputs and scoring.  Returns (q_start, t_start) int32 CUDA
+    tensors (or fills `out`, a pair)."""
+    import torch
+    lib = load()
+    n = q_offsets.numel() - 1
+    for name, t in zip(("score", "q_end", "t_end"), answers):
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("%s must be a contiguous int32 CUDA tensor of n_pairs" % name)
+    if out is None:
+        dev = q_offsets.device
+        out = tuple(torch.empty(max(n, 0), dtype=torch.int32, device=dev) for _ in range(2))
+    sc = Scoring(*[int(x) for x in scoring])
+    opts = make_options(**options)
+    st = lib.salo_align_starts(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                               t_offsets.data_ptr(), n, sc, answers[0].data_ptr(),
+                               answers[1].data_ptr(), answers[2].data_ptr(), out[0].data_ptr(),
+                               out[1].data_ptr(), _stream_handle(stream), ctypes.byref(opts))
     _check(lib, st)
     return out
 

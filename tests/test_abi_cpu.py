@@ -30,7 +30,8 @@ def test_header_declares_the_boundary():
     names = _declared_functions()
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
               "salo_error_count", "salo_last_timing", "salo_set_bins", "salo_get_bins",
-              "salo_last_error", "salo_release", "salo_version", "salo_pack_bases"]:
+              "salo_last_error", "salo_release", "salo_version", "salo_pack_bases",
+              "salo_align_starts"]:
         assert n in names
 
 
@@ -137,3 +138,20 @@ def test_pack_validation(lib):
     assert _pack(16, packed=ADDR + 2) == -1
     assert _pack(16, off=ADDR + 4, revcomp=1) == -1
     assert _pack(16, inv=ADDR + 4) == -1
+
+
+def _starts(n, ptr=ADDR, ans=ADDR, opts=None):
+    o = opts if opts is not None else salo.make_options()
+    return salo.load().salo_align_starts(ptr, ptr, ptr, ptr, n, SC, ans, ans, ans, ptr, ptr,
+                                         NULL, ctypes.byref(o))
+
+
+def test_starts_validation(lib):
+    assert _starts(0, ptr=None, ans=None) == 0
+    assert _starts(-1) == -1
+    assert _starts(5, ans=None) == -1
+    assert _starts(5, ans=ADDR + 2) == -1
+    assert _starts(5, ptr=ADDR + 1) == -1
+    o = salo.make_options(mode="plain")
+    assert _starts(5, opts=o) == -5
+    assert "persistent" in lib.salo_last_error().decode()
