@@ -53,10 +53,17 @@ static inline int base_at(const uint8_t *packed, int64_t k)
     return (packed[k >> 2] >> (2 * (k & 3))) & 3;
 }
 
+/* N masks (optional): bit k of the 32-bit word k>>5 set means base k is N.
+ * An N against any base, N included, scores mismatch. */
+static inline int is_n(const uint32_t *mask, int64_t k)
+{
+    return mask != NULL && ((mask[k >> 5] >> (k & 31)) & 1u);
+}
+
 /* One pair, Eq. 1 row by row.  Rows i = target bases, columns j = query
  * bases.  Hrow/Frow hold row i-1 while row i is being filled. */
-static void gotoh_pair(const uint8_t *q, int64_t q0, int64_t m,
-                       const uint8_t *t, int64_t t0, int64_t n,
+static void gotoh_pair(const uint8_t *q, const uint32_t *qn, int64_t q0, int64_t m,
+                       const uint8_t *t, const uint32_t *tn, int64_t t0, int64_t n,
                        int64_t match, int64_t mismatch,
                        int64_t alpha, int64_t beta,
                        int64_t *Hrow, int64_t *Frow,
@@ -73,12 +80,14 @@ static void gotoh_pair(const uint8_t *q, int64_t q0, int64_t m,
     }
     for (int64_t i = 0; i < n; ++i) {
         const int ti = base_at(t, t0 + i);
+        const int t_is_n = is_n(tn, t0 + i);
         int64_t h_left = 0;              /* H(i, -1) */
         int64_t e = ORACLE_NEG_INF;      /* E(i, -1) */
         int64_t h_diag = 0;              /* H(i-1, -1) */
         for (int64_t j = 0; j < m; ++j) {
             const int qj = base_at(q, q0 + j);
-            const int64_t s = (ti == qj) ? match : mismatch;
+            const int64_t s_acgt = (ti == qj) ? match : mismatch;
+            const int64_t s = (t_is_n || is_n(qn, q0 + j)) ? mismatch : s_acgt;
             /* E(i,j) from H(i,j-1) and E(i,j-1) */
             const int64_t e_open = h_left - alpha;
             const int64_t e_ext = e - beta;
@@ -108,6 +117,7 @@ static void gotoh_pair(const uint8_t *q, int64_t q0, int64_t m,
 
 typedef struct {
     const uint8_t *q, *t;
+    const uint32_t *qn, *tn;
     const int64_t *q_off, *t_off;
     const int64_t *order;
     int64_t n;
@@ -137,7 +147,7 @@ static void *worker(void *arg)
             const int64_t p = jb->order ? jb->order[k] : k;
             const int64_t q0 = jb->q_off[p], q1 = jb->q_off[p + 1];
             const int64_t t0 = jb->t_off[p], t1 = jb->t_off[p + 1];
-            gotoh_pair(jb->q, q0, q1 - q0, jb->t, t0, t1 - t0,
+            gotoh_pair(jb->q, jb->qn, q0, q1 - q0, jb->t, jb->tn, t0, t1 - t0,
                        jb->match, jb->mismatch, jb->alpha, jb->beta,
                        Hrow, Frow, &jb->score[p], &jb->qend[p], &jb->tend[p]);
         }
@@ -160,13 +170,15 @@ static int cmp_cells_desc(const void *a, const void *b)
  * outputs are int64 arrays of length n_pairs.  nthreads <= 0 means 1.
  * Returns 0 on success, -1 on allocation failure.
  */
-int oracle_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
-                       const uint8_t *t_seqs, const int64_t *t_offsets,
-                       int64_t n_pairs,
-                       int64_t match, int64_t mismatch,
-                       int64_t gap_open, int64_t gap_extend,
-                       int64_t *out_score, int64_t *out_qend, int64_t *out_tend,
-                       int nthreads)
+int oracle_align_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
+                         const int64_t *q_offsets,
+                         const uint8_t *t_seqs, const uint32_t *t_nmask,
+                         const int64_t *t_offsets,
+                         int64_t n_pairs,
+                         int64_t match, int64_t mismatch,
+                         int64_t gap_open, int64_t gap_extend,
+                         int64_t *out_score, int64_t *out_qend, int64_t *out_tend,
+                         int nthreads)
 {
     if (n_pairs <= 0) return 0;
     if (nthreads <= 0) nthreads = 1;
@@ -175,6 +187,7 @@ int oracle_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
     job_t jb;
     memset(&jb, 0, sizeof jb);
     jb.q = q_seqs; jb.t = t_seqs; jb.q_off = q_offsets; jb.t_off = t_offsets;
+    jb.qn = q_nmask; jb.tn = t_nmask;
     jb.n = n_pairs;
     jb.match = match; jb.mismatch = mismatch;
     jb.alpha = gap_open + gap_extend;   /* opening a gap of length 1 */
@@ -217,6 +230,20 @@ int oracle_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
     free(cells);
     free(order);
     return rc;
+}
+
+/* Without N masks: every base is A, C, G or T. */
+int oracle_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
+                       const uint8_t *t_seqs, const int64_t *t_offsets,
+                       int64_t n_pairs,
+                       int64_t match, int64_t mismatch,
+                       int64_t gap_open, int64_t gap_extend,
+                       int64_t *out_score, int64_t *out_qend, int64_t *out_tend,
+                       int nthreads)
+{
+    return oracle_align_batch_n(q_seqs, NULL, q_offsets, t_seqs, NULL, t_offsets, n_pairs,
+                                match, mismatch, gap_open, gap_extend, out_score, out_qend,
+                                out_tend, nthreads);
 }
 
 /* H value of one cell, for validity checks of an end position: returns

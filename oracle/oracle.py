@@ -59,6 +59,14 @@ def _load():
             lib.oracle_cell_h.restype = i64
             lib.oracle_pack.argtypes = [p, i64, p, i64, ctypes.c_int, p]
             lib.oracle_pack.restype = i64
+            lib.oracle_pack_n.argtypes = [p, i64, p, i64, ctypes.c_int, p, p]
+            lib.oracle_pack_n.restype = i64
+            lib.oracle_align_batch_n.argtypes = [p, p, p, p, p, p, i64, i64, i64, i64, i64,
+                                                 p, p, p, ctypes.c_int]
+            lib.oracle_align_batch_n.restype = ctypes.c_int
+            lib.oracle_start_batch_n.argtypes = [p, p, p, p, p, p, i64, i64, i64, i64, i64,
+                                                 p, p, p, p, p]
+            lib.oracle_start_batch_n.restype = i64
             lib.oracle_start_batch.argtypes = [p, p, p, p, i64, i64, i64, i64, i64,
                                                p, p, p, p, p]
             lib.oracle_start_batch.restype = i64
@@ -70,6 +78,18 @@ def _ptr(a: np.ndarray) -> int:
     return a.ctypes.data
 
 
+def _mask_ptr(mask, n_bases):
+    """(address or None, array kept alive) of an optional N mask."""
+    if mask is None:
+        return None, None
+    m = np.ascontiguousarray(mask, dtype=np.uint32)
+    if m.size * 32 < int(n_bases):
+        raise ValueError("N mask shorter than the stream")
+    if m.size == 0:
+        m = np.zeros(1, np.uint32)
+    return m.ctypes.data, m
+
+
 def default_threads() -> int:
     try:
         return max(1, len(os.sched_getaffinity(0)))
@@ -78,13 +98,15 @@ def default_threads() -> int:
 
 
 def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
-                nthreads: int | None = None):
+                nthreads: int | None = None, q_nmask=None, t_nmask=None):
     """Oracle alignment of every pair.
 
     q_seqs/t_seqs: uint8 arrays of 2-bit packed bases (4 per byte, LSB first).
     q_offsets/t_offsets: int64 arrays of length n_pairs+1 (CSR, in bases).
     scoring: (match, mismatch, gap_open, gap_extend); a gap of k bases costs
     gap_open + k*gap_extend.
+    q_nmask/t_nmask: optional uint32 arrays, bit k of word k>>5 marking base
+    k of the stream as N (an N scores mismatch against every base).
     Returns (score, q_end, t_end) as int64 arrays.
     """
     lib = _load()
@@ -108,10 +130,12 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
     qb = q_seqs if len(q_seqs) else np.zeros(1, np.uint8)
     tb = t_seqs if len(t_seqs) else np.zeros(1, np.uint8)
     a, b, o, e = (int(x) for x in scoring)
-    rc = lib.oracle_align_batch(_ptr(qb), _ptr(q_offsets), _ptr(tb),
-                                _ptr(t_offsets), n, a, b, o, e, _ptr(score),
-                                _ptr(qend), _ptr(tend),
-                                int(nthreads or default_threads()))
+    qm = _mask_ptr(q_nmask, q_offsets[-1])
+    tm = _mask_ptr(t_nmask, t_offsets[-1])
+    rc = lib.oracle_align_batch_n(_ptr(qb), qm[0], _ptr(q_offsets), _ptr(tb), tm[0],
+                                  _ptr(t_offsets), n, a, b, o, e, _ptr(score),
+                                  _ptr(qend), _ptr(tend),
+                                  int(nthreads or default_threads()))
     if rc != 0:
         raise MemoryError("oracle_align_batch failed (%d)" % rc)
     return score, qend, tend
@@ -151,11 +175,12 @@ def _pack_strings(seqs):
     return np.frombuffer(bytes(buf), dtype=np.uint8), np.array(offs, np.int64)
 
 
-def pack(chars, offsets=None, revcomp: bool = False):
+def pack(chars, offsets=None, revcomp: bool = False, nmask: bool = False):
     """Oracle packing of character reads into the 2-bit stream (see the
     header of pack_oracle.c).  chars: uint8 array; offsets: int64 CSR of the
     sequences (needed for revcomp).  Returns (packed uint8 array of
-    ceil(n/16)*4 bytes, number of invalid bases)."""
+    ceil(n/16)*4 bytes, number of invalid bases), plus the N mask (uint32,
+    ceil(n/32) words) when nmask is true (N and n then count as bases)."""
     lib = _load()
     chars = np.ascontiguousarray(chars, dtype=np.uint8)
     n = chars.size
@@ -163,13 +188,17 @@ def pack(chars, offsets=None, revcomp: bool = False):
         offsets = np.array([0, n], np.int64)
     offsets = np.ascontiguousarray(offsets, dtype=np.int64)
     out = np.zeros(((n + 15) // 16) * 4, np.uint8)
-    bad = lib.oracle_pack(_ptr(chars) if n else None, n, _ptr(offsets), offsets.size - 1,
-                          1 if revcomp else 0, _ptr(out) if out.size else None)
+    mask = np.zeros(max((n + 31) // 32, 1), np.uint32) if nmask else None
+    bad = lib.oracle_pack_n(_ptr(chars) if n else None, n, _ptr(offsets), offsets.size - 1,
+                            1 if revcomp else 0, _ptr(out) if out.size else None,
+                            _ptr(mask) if nmask else None)
+    if nmask:
+        return out, int(bad), mask[: (n + 31) // 32]
     return out, int(bad)
 
 
 def start_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_end, t_end,
-                scoring=(1, -4, 6, 1)):
+                scoring=(1, -4, 6, 1), q_nmask=None, t_nmask=None):
     """Oracle start positions (see the header of start_oracle.c) of the best
     alignments whose score and end are given (the answers of align_batch).
     Returns (q_start, t_start) int64 arrays; raises if an anchored maximum
@@ -186,9 +215,11 @@ def start_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_end, t_end,
     q_offsets = np.ascontiguousarray(q_offsets, dtype=np.int64)
     t_offsets = np.ascontiguousarray(t_offsets, dtype=np.int64)
     a, b, o, e = scoring
-    bad = lib.oracle_start_batch(_ptr(q_seqs), _ptr(q_offsets), _ptr(t_seqs), _ptr(t_offsets),
-                                 n, a, b, o, e, _ptr(arrs[0]), _ptr(arrs[1]), _ptr(arrs[2]),
-                                 _ptr(qs), _ptr(ts))
+    qm = _mask_ptr(q_nmask, q_offsets[-1])
+    tm = _mask_ptr(t_nmask, t_offsets[-1])
+    bad = lib.oracle_start_batch_n(_ptr(q_seqs), qm[0], _ptr(q_offsets), _ptr(t_seqs), tm[0],
+                                   _ptr(t_offsets), n, a, b, o, e, _ptr(arrs[0]),
+                                   _ptr(arrs[1]), _ptr(arrs[2]), _ptr(qs), _ptr(ts))
     if bad != 0:
         raise RuntimeError("start oracle: %d pairs whose anchored maximum is not the score" % bad)
     return qs, ts

@@ -40,24 +40,35 @@ static int char_code(uint8_t c, int *code) {
     }
 }
 
-/* Returns the number of invalid bases; writes ceil(n_chars/16)*4 bytes. */
-int64_t oracle_pack(const uint8_t *chars, int64_t n_chars, const int64_t *off,
-                    int64_t n_seqs, int revcomp, uint8_t *out) {
+/* Returns the number of invalid bases; writes ceil(n_chars/16)*4 bytes.
+ * With nmask (ceil(n_chars/32) 32-bit words, or NULL): N and n are bases,
+ * written as 0 with bit k of the mask set (the complement of N is N);
+ * without it they are invalid like any other character. */
+int64_t oracle_pack_n(const uint8_t *chars, int64_t n_chars, const int64_t *off,
+                      int64_t n_seqs, int revcomp, uint8_t *out, uint32_t *nmask) {
     const int64_t out_bytes = ((n_chars + 15) / 16) * 4;
     memset(out, 0, (size_t)out_bytes);
+    if (nmask) memset(nmask, 0, (size_t)((n_chars + 31) / 32) * 4);
     int64_t invalid = 0;
     int64_t s = 0;                     /* sequence holding base k (revcomp) */
     for (int64_t k = 0; k < n_chars; ++k) {
         int code = 0, ok = 0;
+        int64_t src = k;
         if (!revcomp) {
             ok = char_code(chars[k], &code);
         } else {
+            src = -1;
             while (s < n_seqs && off[s + 1] <= k) ++s;
             if (s < n_seqs && off[s] <= k && k < off[s + 1]) {
-                const int64_t src = off[s] + off[s + 1] - 1 - k;
+                src = off[s] + off[s + 1] - 1 - k;
                 ok = char_code(chars[src], &code);
                 if (ok) code = 3 - code;
             }
+        }
+        if (!ok && nmask && src >= 0 && (chars[src] == 'N' || chars[src] == 'n')) {
+            nmask[k >> 5] |= 1u << (k & 31);
+            ok = 1;
+            code = 0;
         }
         if (!ok) {
             ++invalid;
@@ -66,4 +77,10 @@ int64_t oracle_pack(const uint8_t *chars, int64_t n_chars, const int64_t *off,
         out[k >> 2] |= (uint8_t)(code << (2 * (k & 3)));
     }
     return invalid;
+}
+
+/* Without an N mask. */
+int64_t oracle_pack(const uint8_t *chars, int64_t n_chars, const int64_t *off,
+                    int64_t n_seqs, int revcomp, uint8_t *out) {
+    return oracle_pack_n(chars, n_chars, off, n_seqs, revcomp, out, NULL);
 }

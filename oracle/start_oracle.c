@@ -46,18 +46,27 @@ static inline int start_base(const uint8_t *packed, int64_t k)
     return (packed[k >> 2] >> (2 * (k & 3))) & 3;
 }
 
+/* Optional N masks (bit k of word k>>5): an N scores mismatch against
+ * every base, N included. */
+static inline int start_is_n(const uint32_t *mask, int64_t k)
+{
+    return mask != NULL && ((mask[k >> 5] >> (k & 31)) & 1u);
+}
+
 /*
  * For every pair p with score[p] > 0, writes q_start / t_start (else -1).
  * Returns the number of pairs whose anchored maximum differed from score[p]
  * (0 when the inputs are the alignment oracle's answers), or -1 when memory
  * runs out.
  */
-int64_t oracle_start_batch(const uint8_t *q_seqs, const int64_t *q_off,
-                           const uint8_t *t_seqs, const int64_t *t_off,
-                           int64_t n_pairs, int64_t match, int64_t mismatch,
-                           int64_t gap_open, int64_t gap_extend,
-                           const int64_t *score, const int64_t *qend, const int64_t *tend,
-                           int64_t *out_qstart, int64_t *out_tstart)
+int64_t oracle_start_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
+                             const int64_t *q_off,
+                             const uint8_t *t_seqs, const uint32_t *t_nmask,
+                             const int64_t *t_off,
+                             int64_t n_pairs, int64_t match, int64_t mismatch,
+                             int64_t gap_open, int64_t gap_extend,
+                             const int64_t *score, const int64_t *qend, const int64_t *tend,
+                             int64_t *out_qstart, int64_t *out_tstart)
 {
     const int64_t alpha = gap_open + gap_extend, beta = gap_extend;
     int64_t bad = 0;
@@ -77,12 +86,15 @@ int64_t oracle_start_batch(const uint8_t *q_seqs, const int64_t *q_off,
         int64_t best = START_NEG_INF, bi = -1, bj = -1;
         for (int64_t i = 0; i <= te; ++i) {
             const int ti = start_base(t_seqs, t_off[p] + te - i);
+            const int t_is_n = start_is_n(t_nmask, t_off[p] + te - i);
             int64_t a_left = START_NEG_INF;        /* A(i', -1) */
             int64_t e = START_NEG_INF;             /* E(i', -1) */
             int64_t a_diag = i == 0 ? 0 : START_NEG_INF;   /* A(i'-1, -1): the anchor */
             for (int64_t j = 0; j < mq; ++j) {
                 const int qj = start_base(q_seqs, q_off[p] + qe - j);
-                const int64_t s = (ti == qj) ? match : mismatch;
+                const int64_t s_acgt = (ti == qj) ? match : mismatch;
+                const int64_t s =
+                    (t_is_n || start_is_n(q_nmask, q_off[p] + qe - j)) ? mismatch : s_acgt;
                 const int64_t e_open = a_left - alpha, e_ext = e - beta;
                 e = e_open > e_ext ? e_open : e_ext;
                 const int64_t f_open = Arow[j] - alpha, f_ext = Frow[j] - beta;
@@ -104,4 +116,17 @@ int64_t oracle_start_batch(const uint8_t *q_seqs, const int64_t *q_off,
         out_tstart[p] = te - bi;
     }
     return bad;
+}
+
+/* Without N masks. */
+int64_t oracle_start_batch(const uint8_t *q_seqs, const int64_t *q_off,
+                           const uint8_t *t_seqs, const int64_t *t_off,
+                           int64_t n_pairs, int64_t match, int64_t mismatch,
+                           int64_t gap_open, int64_t gap_extend,
+                           const int64_t *score, const int64_t *qend, const int64_t *tend,
+                           int64_t *out_qstart, int64_t *out_tstart)
+{
+    return oracle_start_batch_n(q_seqs, NULL, q_off, t_seqs, NULL, t_off, n_pairs, match,
+                                mismatch, gap_open, gap_extend, score, qend, tend,
+                                out_qstart, out_tstart);
 }

@@ -26,7 +26,8 @@ NEG = None
 
 
 def _s(tb, qb, a, b):
-    return a if tb == qb else b
+    # N (unknown base) scores the mismatch against every base, N included
+    return a if tb == qb and tb != "N" else b
 
 
 def enumerate_h(q, t, scoring):

@@ -140,8 +140,8 @@ MUTANTS = {
     "msb_first": ("out[k >> 2] |= (uint8_t)(code << (2 * (k & 3)));",
                   "out[k >> 2] |= (uint8_t)(code << (6 - 2 * (k & 3)));"),
     "mirror_off_by_one": ("off[s] + off[s + 1] - 1 - k", "off[s] + off[s + 1] - k"),
-    "mirror_whole_stream": ("const int64_t src = off[s] + off[s + 1] - 1 - k;",
-                            "const int64_t src = off[n_seqs] - 1 - k;"),
+    "mirror_whole_stream": ("src = off[s] + off[s + 1] - 1 - k;",
+                            "src = off[n_seqs] - 1 - k;"),
     "upper_case_only": ("case 'A': case 'a':", "case 'A':"),
     "invalid_not_counted": ("++invalid;\n            code = 0;", "code = 0;"),
     "g_and_c_swapped": ("case 'C': case 'c': *code = 1;", "case 'C': case 'c': *code = 2;"),

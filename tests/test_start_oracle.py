@@ -142,7 +142,8 @@ def test_equals_local_alignment_of_reversed_prefixes():
 # answers (see the test above), so neither is a mistake to plant.
 MUTANTS = {
     "last_max": ("if (a > best) { best = a;", "if (a >= best) { best = a;"),
-    "mirror_off_by_one": ("t_off[p] + te - i", "t_off[p] + te - i - 1"),
+    "mirror_off_by_one": ("start_base(t_seqs, t_off[p] + te - i)",
+                          "start_base(t_seqs, t_off[p] + te - i - 1)"),
     "alpha_is_extend": ("const int64_t alpha = gap_open + gap_extend,", "const int64_t alpha = gap_extend,"),
     "start_not_mirrored": ("out_qstart[p] = qe - bj;", "out_qstart[p] = bj;"),
 }
