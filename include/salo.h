@@ -139,6 +139,23 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
                                   const salo_options_t *opts);
 
 /*
+ * As salo_align_batch_ex, for reads with unknown bases (N; the paper's
+ * five-letter reads, Section II-B).  q_nmask / t_nmask: DEVICE uint32
+ * arrays, 4-byte aligned, one bit per base of the stream (bit k of word k>>5
+ * set: base k is N; its 2-bit code is ignored), covering
+ * ceil(offsets[n_pairs] / 32) words; either may be NULL (no N in that
+ * stream).  An N scores `mismatch` against every base, N included.  With a
+ * mask the 16-bit integer and 32-bit cells are used (binary16 cells are
+ * off) and the default grid is 8 waves per CU.
+ */
+salo_status_t salo_align_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
+                                 const int64_t *q_offsets, const uint8_t *t_seqs,
+                                 const uint32_t *t_nmask, const int64_t *t_offsets,
+                                 int64_t n_pairs, salo_scoring_t scoring, int32_t *out_score,
+                                 int32_t *out_qend, int32_t *out_tend, hipStream_t stream,
+                                 const salo_options_t *opts);
+
+/*
  * Start positions of the answers of a previous align call: where the
  * optimal path to the highest cell (Section II-A) begins.  For every pair
  * with score > 0 ending at (q_end, t_end), out_qstart / out_tstart receive
@@ -148,7 +165,8 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
  * reversed prefixes q[q_end..0], t[t_end..0] (it equals the score exactly
  * at the optimal starts, because (q_end, t_end) is the first maximum of the
  * whole table).
- * Arguments: the align call's sequences, offsets, n_pairs and scoring; its
+ * Arguments: the align call's sequences, N masks (NULL for none, see
+ * salo_align_batch_n), offsets, n_pairs and scoring; its
  * three outputs score, q_end, t_end (DEVICE int32 [n_pairs], 4-byte
  * aligned); out_qstart, out_tstart (DEVICE int32 [n_pairs], fully
  * overwritten; -1 for pairs with score 0).  A pair whose given answer is
@@ -158,8 +176,9 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
  * SALO_ERR_UNSUPPORTED); other options and all errors as
  * salo_align_batch_ex.
  */
-salo_status_t salo_align_starts(const uint8_t *q_seqs, const int64_t *q_offsets,
-                                const uint8_t *t_seqs, const int64_t *t_offsets,
+salo_status_t salo_align_starts(const uint8_t *q_seqs, const uint32_t *q_nmask,
+                                const int64_t *q_offsets, const uint8_t *t_seqs,
+                                const uint32_t *t_nmask, const int64_t *t_offsets,
                                 int64_t n_pairs, salo_scoring_t scoring, const int32_t *score,
                                 const int32_t *q_end, const int32_t *t_end,
                                 int32_t *out_qstart, int32_t *out_tstart, hipStream_t stream,
@@ -198,9 +217,10 @@ salo_status_t salo_get_bins(salo_bin_t *bins, int32_t max_bins, int32_t *n_bins)
  * carry one byte per base, SALoBa Section II-B; the evaluation packs them
  * on the device for every method, Section V-A).
  *
- * chars: DEVICE, n_chars bytes, the concatenated sequences, 4-byte aligned.
- *   A, C, G, T are accepted in either case; any other byte is an invalid
- *   base, written as A (0) and counted.
+ * chars: DEVICE, n_chars bytes, the concatenated sequences, 4-byte aligned
+ *   and readable up to the next multiple of 4 bytes.  A, C, G, T are
+ *   accepted in either case; N and n too when n_mask is given; any other
+ *   byte is an invalid base, written as A (0) and counted.
  * offsets: DEVICE int64 [n_seqs+1], 8-byte aligned, the sequences' CSR in
  *   characters (non-decreasing, offsets[0] = 0, offsets[n_seqs] = n_chars).
  *   Read only when revcomp = 1 (it may be NULL otherwise).
@@ -214,6 +234,10 @@ salo_status_t salo_get_bins(salo_bin_t *bins, int32_t max_bins, int32_t *n_bins)
  *   base are 0).  It must not overlap chars.  The output offsets of the
  *   sequences equal the input offsets (one base per character), so
  *   (packed, offsets) can be passed straight to the align calls.
+ * n_mask: DEVICE uint32 [ceil(n_chars/32)], 4-byte aligned, or NULL: bit k
+ *   of word k>>5 is set when output base k is N (its 2-bit code is 0); the
+ *   complement of N is N.  (packed, n_mask) go straight to
+ *   salo_align_batch_n.
  * invalid_count: DEVICE counter or NULL; the kernel adds the number of
  *   invalid bases to it (the caller clears it).
  * Asynchronous on `stream`; host-checkable errors (n_chars < 0, NULL or
@@ -222,7 +246,8 @@ salo_status_t salo_get_bins(salo_bin_t *bins, int32_t max_bins, int32_t *n_bins)
  */
 salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
                               int64_t n_seqs, int32_t revcomp, uint8_t *packed,
-                              unsigned long long *invalid_count, hipStream_t stream);
+                              uint32_t *n_mask, unsigned long long *invalid_count,
+                              hipStream_t stream);
 
 /* Message for the last non-OK status returned on this host thread. */
 const char *salo_last_error(void);

@@ -196,12 +196,15 @@ salo_status_t validate(const uint8_t *q_seqs, const int64_t *q_offsets, const ui
 struct StartArgs {
     const int32_t *score, *qend, *tend;
 };
+struct NMasks {
+    const uint32_t *q, *t;   // either may be nullptr
+};
 
 salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
                         const uint8_t *t_seqs, const int64_t *t_offsets, int64_t n_pairs,
                         salo_scoring_t scoring, int32_t *out_score, int32_t *out_qend,
                         int32_t *out_tend, hipStream_t stream, const salo_options_t *opts,
-                        const StartArgs *starts) {
+                        const StartArgs *starts, NMasks masks) {
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
@@ -221,8 +224,10 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
 
     // resident waves per CU at the kernel's register budget: 3 per SIMD for
     // 8 or 16 query columns per lane, 2 per SIMD for 32
+    // (kernels that read N masks are compiled for 2 per SIMD)
+    const bool nm = masks.q != nullptr || masks.t != nullptr;
     const int cols_req = o.cols ? o.cols : 16;
-    const int wpc = o.waves_per_cu ? o.waves_per_cu : (cols_req >= 32 ? 8 : 12);
+    const int wpc = o.waves_per_cu ? o.waves_per_cu : (cols_req >= 32 || nm ? 8 : 12);
     const int64_t grid = (int64_t)ws->cus * wpc;
     st = ensure_slots(*ws, grid, stream);
     if (st != SALO_OK) return st;
@@ -242,8 +247,11 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     p.errors = ws->errors;
     p.force_int32 = o.force_int32 ? 1 : 0;
     p.packed_ok = scoring_packed_ok(scoring.match, scoring.mismatch) ? 1 : 0;
-    p.half_ok = !o.no_f16 && scoring_half_ok(scoring.match, scoring.mismatch,
-                                             scoring.gap_open, scoring.gap_extend);
+    p.q_nmask = masks.q;
+    p.t_nmask = masks.t;
+    // binary16 cells cannot give an N column the mismatch: off with masks
+    p.half_ok = !o.no_f16 && !nm && scoring_half_ok(scoring.match, scoring.mismatch,
+                                                    scoring.gap_open, scoring.gap_extend);
     p.bins = ws->bins;
     p.unit_counter = ws->counters;
     p.total_units = ws->counters + 1;
@@ -312,11 +320,27 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
                                 out_score, out_qend, out_tend);
     if (st != SALO_OK) return st;
     return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
-                     out_qend, out_tend, stream, opts, nullptr);
+                     out_qend, out_tend, stream, opts, nullptr, NMasks{nullptr, nullptr});
 }
 
-salo_status_t salo_align_starts(const uint8_t *q_seqs, const int64_t *q_offsets,
-                                const uint8_t *t_seqs, const int64_t *t_offsets,
+salo_status_t salo_align_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
+                                 const int64_t *q_offsets, const uint8_t *t_seqs,
+                                 const uint32_t *t_nmask, const int64_t *t_offsets,
+                                 int64_t n_pairs, salo_scoring_t scoring, int32_t *out_score,
+                                 int32_t *out_qend, int32_t *out_tend, hipStream_t stream,
+                                 const salo_options_t *opts) {
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                out_score, out_qend, out_tend);
+    if (st != SALO_OK) return st;
+    if ((reinterpret_cast<uintptr_t>(q_nmask) | reinterpret_cast<uintptr_t>(t_nmask)) & 3)
+        return fail(SALO_ERR_INVALID, "N masks must be 4-byte aligned");
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
+                     out_qend, out_tend, stream, opts, nullptr, NMasks{q_nmask, t_nmask});
+}
+
+salo_status_t salo_align_starts(const uint8_t *q_seqs, const uint32_t *q_nmask,
+                                const int64_t *q_offsets, const uint8_t *t_seqs,
+                                const uint32_t *t_nmask, const int64_t *t_offsets,
                                 int64_t n_pairs, salo_scoring_t scoring, const int32_t *score,
                                 const int32_t *q_end, const int32_t *t_end,
                                 int32_t *out_qstart, int32_t *out_tstart, hipStream_t stream,
@@ -329,9 +353,11 @@ salo_status_t salo_align_starts(const uint8_t *q_seqs, const int64_t *q_offsets,
     if ((reinterpret_cast<uintptr_t>(score) | reinterpret_cast<uintptr_t>(q_end) |
          reinterpret_cast<uintptr_t>(t_end)) & 3)
         return fail(SALO_ERR_INVALID, "score / q_end / t_end must be 4-byte aligned");
+    if ((reinterpret_cast<uintptr_t>(q_nmask) | reinterpret_cast<uintptr_t>(t_nmask)) & 3)
+        return fail(SALO_ERR_INVALID, "N masks must be 4-byte aligned");
     const StartArgs sa{score, q_end, t_end};
     return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, nullptr,
-                     out_qstart, out_tstart, stream, opts, &sa);
+                     out_qstart, out_tstart, stream, opts, &sa, NMasks{q_nmask, t_nmask});
 }
 
 salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
@@ -452,7 +478,8 @@ void salo_release(void) {
 
 salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
                               int64_t n_seqs, int32_t revcomp, uint8_t *packed,
-                              unsigned long long *invalid_count, hipStream_t stream) {
+                              uint32_t *n_mask, unsigned long long *invalid_count,
+                              hipStream_t stream) {
     if (n_chars < 0) return fail(SALO_ERR_INVALID, "n_chars < 0");
     if (n_seqs < 0) return fail(SALO_ERR_INVALID, "n_seqs < 0");
     if (revcomp != 0 && revcomp != 1) return fail(SALO_ERR_INVALID, "revcomp must be 0 or 1");
@@ -465,8 +492,10 @@ salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64
         return fail(SALO_ERR_INVALID, "offsets must be 8-byte aligned");
     if (invalid_count && (reinterpret_cast<uintptr_t>(invalid_count) & 7))
         return fail(SALO_ERR_INVALID, "invalid_count must be 8-byte aligned");
+    if (n_mask && (reinterpret_cast<uintptr_t>(n_mask) & 3))
+        return fail(SALO_ERR_INVALID, "n_mask must be 4-byte aligned");
     const hipError_t e = launch_pack(chars, n_chars, revcomp ? offsets : nullptr, n_seqs,
-                                     revcomp != 0, packed, invalid_count, stream);
+                                     revcomp != 0, packed, n_mask, invalid_count, stream);
     if (e != hipSuccess) return hip_fail(e, "launch pack kernel");
     return SALO_OK;
 }

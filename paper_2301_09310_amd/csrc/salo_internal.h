@@ -73,6 +73,10 @@ struct KParams {
     const int32_t *in_score;
     const int32_t *in_qend;
     const int32_t *in_tend;
+    // optional N masks (bit k of word k>>5 marks base k of the stream as N;
+    // an N scores mismatch against every base); nullptr: no N
+    const uint32_t *q_nmask;
+    const uint32_t *t_nmask;
     int32_t force_int32;
     int32_t packed_ok;             // scoring admits 16-bit packed cells
     int32_t half_ok;               // scoring admits binary16 cells (and no_f16 is off)
@@ -134,7 +138,7 @@ hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,
                         hipStream_t stream);
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream);
 hipError_t launch_pack(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
-                       int64_t n_seqs, bool revcomp, uint8_t *packed,
+                       int64_t n_seqs, bool revcomp, uint8_t *packed, uint32_t *n_mask,
                        unsigned long long *invalid, hipStream_t stream);
 bool persistent_lanes_supported(int lanes);
 

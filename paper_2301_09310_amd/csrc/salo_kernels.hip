@@ -105,6 +105,21 @@ struct BaseStream {
         base = p;
         nbytes = __builtin_amdgcn_readfirstlane((int)(uint32_t)bytes);
     }
+    // an N-mask stream: one bit per base, 32 bases per word
+    __device__ __forceinline__ void init_mask(const uint32_t *p, const int64_t *off,
+                                              int64_t n_pairs) {
+        int64_t bases = (p != nullptr && n_pairs > 0) ? off[n_pairs] : 0;
+        int64_t bytes = ((bases + 31) >> 5) << 2;
+        if (bytes < 0) bytes = 0;
+        if (bytes > 0xFFFFFFF0ll) bytes = 0xFFFFFFF0ll;
+        base = reinterpret_cast<const uint8_t *>(p);
+        nbytes = __builtin_amdgcn_readfirstlane((int)(uint32_t)bytes);
+    }
+    // the 32 mask bits of bases pos .. pos+31 (bit 0 = base pos)
+    __device__ __forceinline__ uint32_t bits32(int64_t pos) const {
+        const int64_t w = pos >> 5;
+        return __builtin_amdgcn_alignbit(word(w + 1), word(w), (uint32_t)(pos & 31));
+    }
     __device__ __forceinline__ uint32_t word(int64_t w) const {
         // the descriptor is rebuilt from scalar values at every use so that
         // it stays in SGPRs (no waterfall loop)
@@ -268,8 +283,9 @@ enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
 // pos0: first position (in processing order) of the unit's pairs.
 // [g0, g0 + gn): the groups processed in this pass (all G normally; fewer
 // when the unit's boundary columns do not fit one slot together).
-template <int K, int CT, bool REV>
+template <int K, int CT, bool REV, bool NM>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
+                                         BaseStream qm, BaseStream tm,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
                          uint32_t *slot, uint32_t *lds_saved) {
     const int G = kWave / W;
@@ -354,6 +370,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             // this lane's query bases as up to two 16-base words per pair
             constexpr int NQW = (K + 15) / 16;
             uint32_t qw[NPG][NQW];
+            // NM: N bits of the lane's columns (bit k = column col0 + k)
+            uint32_t qn[NPG];
+#pragma unroll
+            for (int h = 0; h < NPG; ++h) {
+                qn[h] = 0u;
+                if constexpr (NM) {
+                    if constexpr (REV)
+                        qn[h] = __builtin_bitreverse32(qm.bits32(pr[h].q0 - col0 - 31));
+                    else
+                        qn[h] = qm.bits32(pr[h].q0 + col0);
+                }
+            }
 #pragma unroll
             for (int h = 0; h < NPG; ++h) {
                 // REV: column col0 + k is base q0 - col0 - k, so read the
@@ -380,9 +408,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if constexpr (PK) {
-                    const uint32_t sA = (col0 + k < pr[0].m)
+                    // a column past the query's end, or an N, selects 0:
+                    // a mismatch in 16-bit integers (binary16 never has N)
+                    const uint32_t sA = (col0 + k < pr[0].m && !((qn[0] >> k) & 1u))
                                             ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u) : 12u;
-                    const uint32_t sB = (col0 + k < pr[1].m)
+                    const uint32_t sB = (col0 + k < pr[1].m && !((qn[1] >> k) & 1u))
                                             ? (4u + ((qw[1][k >> 4] >> (2 * (k & 15))) & 3u)) : 12u;
                     // 16-bit integers: table byte low, 0 high; binary16:
                     // 0 low, table byte high (a column past the query's end
@@ -392,8 +422,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     else
                         SEL[k] = (sA << 8) | (sB << 24) | 0x000C000Cu;
                 } else {
-                    SEL[k] = (col0 + k < pr[0].m) ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u)
-                                                  : 5u;
+                    SEL[k] = (col0 + k < pr[0].m && !((qn[0] >> k) & 1u))
+                                 ? ((qw[0][k >> 4] >> (2 * (k & 15))) & 3u) : 5u;
                 }
             }
         }
@@ -437,6 +467,21 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         uint32_t tw[NPG];
 #pragma unroll
         for (int h = 0; h < NPG; ++h) tw[h] = 0;
+        // NM: N bits of the 16 target rows of the current word (bit j = row
+        // s0 + j - l of this lane), and of the next 16, in flight
+        uint32_t tn[NPG], tn_nx[NPG];
+        auto target_n_bits = [&](int h, int s0w) -> uint32_t {
+            if constexpr (REV)
+                return __builtin_bitreverse32(tm.bits32(pr[h].t0 + l - 15 - s0w)) >> 16;
+            else
+                return tm.bits32(pr[h].t0 - l + s0w);
+        };
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) {
+            tn[h] = 0u;
+            tn_nx[h] = 0u;
+            if constexpr (NM) tn_nx[h] = target_n_bits(h, 0);
+        }
         for (int s0 = 0; s0 < S; s0 += 4) {
             if ((s0 & 15) == 0) {
                 // the next 16 target bases of each pair, already in flight;
@@ -448,6 +493,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     const int64_t wi = REV ? twi[h] - ((s0 + 16) >> 4) : twi[h] + ((s0 + 16) >> 4);
                     tw_lo[h] = ts.word(wi);
                     tw_hi[h] = ts.word(wi + 1);
+                    if constexpr (NM) {
+                        tn[h] = tn_nx[h];
+                        tn_nx[h] = target_n_bits(h, s0 + 16);
+                    }
                 }
             }
             const uint32_t jsh = (uint32_t)(s0 & 15) * 2u;
@@ -501,8 +550,16 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 } else if constexpr (CT == kCellU16) {
                     const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
                     const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
-                    const uint32_t TA = (uint32_t)i < (uint32_t)pr[0].n ? (KC << (bA << 3)) : 0u;
-                    const uint32_t TB = (uint32_t)i < (uint32_t)pr[1].n ? (KC << (bB << 3)) : 0u;
+                    // rows past the pair's end (and N rows) get the zero
+                    // table: a mismatch in every column
+                    bool okA = (uint32_t)i < (uint32_t)pr[0].n;
+                    bool okB = (uint32_t)i < (uint32_t)pr[1].n;
+                    if constexpr (NM) {
+                        okA = okA && !((tn[0] >> ((s0 & 15) + j)) & 1u);
+                        okB = okB && !((tn[1] >> ((s0 & 15) + j)) & 1u);
+                    }
+                    const uint32_t TA = okA ? (KC << (bA << 3)) : 0u;
+                    const uint32_t TB = okB ? (KC << (bB << 3)) : 0u;
 #pragma unroll
                     for (int k = K - 1; k >= 0; --k)
                         H[k] = psub(padd(k > 0 ? H[k - 1] : hd,
@@ -521,8 +578,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
                     }
                 } else {
-                    const uint32_t tb = (uint32_t)i < (uint32_t)pr[0].n
-                                            ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
+                    bool okt = (uint32_t)i < (uint32_t)pr[0].n;
+                    if constexpr (NM) okt = okt && !((tn[0] >> ((s0 & 15) + j)) & 1u);
+                    // 4 never equals a query code (0..3, or 5 past the end / N)
+                    const uint32_t tb = okt ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
 #pragma unroll
                     for (int k = K - 1; k >= 0; --k)
                         H[k] = (uint32_t)((int)(k > 0 ? H[k - 1] : hd) +
@@ -628,8 +687,9 @@ __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, in
     return __builtin_amdgcn_readfirstlane(all16 ? (allh ? kCellF16 : kCellU16) : kCellWide);
 }
 
-template <int K, bool REV>
+template <int K, bool REV, bool NM>
 __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, BaseStream ts,
+                                             BaseStream qm, BaseStream tm,
                                              int64_t pos0, int npairs, int W, uint32_t *slot,
                                              uint32_t *lds) {
     const int G = kWave / W;
@@ -646,44 +706,52 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     // instantiation keeps run_unit inlined.
     const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(R, 1)));
     const int passes = (G + fit - 1) / fit;
+    // with N masks the host turns binary16 cells off (their table cannot
+    // give an N column the mismatch), so NM never instantiates them
     const int ct = unit_cell_type<REV>(P, pos0, npairs);
-    if (ct == kCellF16) {
+    if (!NM && ct == kCellF16) {
+        if constexpr (!NM) {
+            for (int ps = 0; ps < passes; ++ps)
+                run_unit<K, kCellF16, REV, false>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
+                                                  ps * fit, min(fit, G - ps * fit), W, slot, lds);
+        }
+    } else if (ct == kCellU16 || ct == kCellF16) {
         for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, kCellF16, REV>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
-                                  min(fit, G - ps * fit), W, slot, lds);
-    } else if (ct == kCellU16) {
-        for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, kCellU16, REV>(P, qs, ts, pos0, pos0 + npairs, ps * fit,
-                                  min(fit, G - ps * fit), W, slot, lds);
+            run_unit<K, kCellU16, REV, NM>(P, qs, ts, qm, tm, pos0, pos0 + npairs, ps * fit,
+                                           min(fit, G - ps * fit), W, slot, lds);
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;
-            run_unit<K, kCellWide, REV>(P, qs, ts, pos0 + (int64_t)half * G, pos0 + npairs,
-                                   ps * fit, min(fit, G - ps * fit), W, slot, lds);
+            run_unit<K, kCellWide, REV, NM>(P, qs, ts, qm, tm, pos0 + (int64_t)half * G,
+                                            pos0 + npairs, ps * fit, min(fit, G - ps * fit), W,
+                                            slot, lds);
         }
     }
 }
 
 // Resident waves per SIMD each width is compiled for: 512 VGPRs per lane
 // hold three waves of at most 168 registers (K <= 16) or two of at most 256
-// (K = 32).  The host sizes the grid to match.
-template <int K> constexpr int kMinWaves = K <= 16 ? 3 : 2;
+// (K = 32, and every kernel that reads N masks).  The host sizes the grid
+// to match.
+template <int K, bool NM = false> constexpr int kMinWaves = (K <= 16 && !NM) ? 3 : 2;
 
 // Plain mode: pairs in input order, fixed lanes/cols, units of 128/W pairs
 // dealt to waves round robin.
-template <int K>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>, 8))) void plain_kernel(KParams P, int W) {
+template <int K, bool NM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM>, 8))) void plain_kernel(KParams P, int W) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
-    BaseStream qs, ts;
+    BaseStream qs, ts, qm, tm;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
     ts.init(P.t_seqs, P.t_off, P.n_pairs);
+    qm.init_mask(P.q_nmask, P.q_off, P.n_pairs);
+    tm.init_mask(P.t_nmask, P.t_off, P.n_pairs);
     const int ppu = 2 * (kWave / W);
     const int64_t n_units = (P.n_pairs + ppu - 1) / ppu;
     uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pos0 = u * ppu;
         const int np = (int)min<int64_t>(ppu, P.n_pairs - pos0);
-        process_unit<K, false>(P, qs, ts, pos0, np, W, slot, lds_saved);
+        process_unit<K, false, NM>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved);
     }
 }
 
@@ -692,13 +760,15 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>
 // atomic counter until the planned units are exhausted.  The lane-group
 // width comes from the unit's bin; the query columns per lane (K) are fixed
 // per launch so every width shares one register budget.  REV is the start
-// pass (reversed prefixes ending at the forward answers).
-template <int K, bool REV>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>, 8))) void persistent_kernel(KParams P) {
+// pass (reversed prefixes ending at the forward answers); NM reads N masks.
+template <int K, bool REV, bool NM>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM>, 8))) void persistent_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
-    BaseStream qs, ts;
+    BaseStream qs, ts, qm, tm;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
     ts.init(P.t_seqs, P.t_off, P.n_pairs);
+    qm.init_mask(P.q_nmask, P.q_off, P.n_pairs);
+    tm.init_mask(P.t_nmask, P.t_off, P.n_pairs);
     uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
     const int lane = threadIdx.x & (kWave - 1);
     const int total = __builtin_amdgcn_readfirstlane(*P.total_units);
@@ -720,7 +790,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K>
         const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
         const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
-        process_unit<K, REV>(P, qs, ts, pos0, np, lanes, slot, lds_saved);
+        process_unit<K, REV, NM>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved);
     }
 }
 
@@ -732,16 +802,22 @@ bool plain_variant_exists(int lanes, int cols) {
     return w && (cols == 8 || cols == 16 || cols == 32);
 }
 
-hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid, hipStream_t stream) {
+template <bool NM>
+hipError_t launch_plain_nm(const KParams &p, int lanes, int cols, int grid, hipStream_t stream) {
     if (cols == 32)
-        hipLaunchKernelGGL((plain_kernel<32>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
+        hipLaunchKernelGGL((plain_kernel<32, NM>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
     else if (cols == 16)
-        hipLaunchKernelGGL((plain_kernel<16>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
+        hipLaunchKernelGGL((plain_kernel<16, NM>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
     else if (cols == 8)
-        hipLaunchKernelGGL((plain_kernel<8>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
+        hipLaunchKernelGGL((plain_kernel<8, NM>), dim3(grid), dim3(kWave), 0, stream, p, lanes);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid, hipStream_t stream) {
+    if (p.q_nmask || p.t_nmask) return launch_plain_nm<true>(p, lanes, cols, grid, stream);
+    return launch_plain_nm<false>(p, lanes, cols, grid, stream);
 }
 
 bool persistent_lanes_supported(int lanes) {
@@ -749,27 +825,26 @@ bool persistent_lanes_supported(int lanes) {
            lanes == 64;
 }
 
-hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream) {
-    if (p.in_score) {
-        if (cols == 32)
-            hipLaunchKernelGGL((persistent_kernel<32, true>), dim3(grid), dim3(kWave), 0, stream, p);
-        else if (cols == 16)
-            hipLaunchKernelGGL((persistent_kernel<16, true>), dim3(grid), dim3(kWave), 0, stream, p);
-        else if (cols == 8)
-            hipLaunchKernelGGL((persistent_kernel<8, true>), dim3(grid), dim3(kWave), 0, stream, p);
-        else
-            return hipErrorInvalidValue;
-    } else {
-        if (cols == 32)
-            hipLaunchKernelGGL((persistent_kernel<32, false>), dim3(grid), dim3(kWave), 0, stream, p);
-        else if (cols == 16)
-            hipLaunchKernelGGL((persistent_kernel<16, false>), dim3(grid), dim3(kWave), 0, stream, p);
-        else if (cols == 8)
-            hipLaunchKernelGGL((persistent_kernel<8, false>), dim3(grid), dim3(kWave), 0, stream, p);
-        else
-            return hipErrorInvalidValue;
-    }
+template <bool REV, bool NM>
+hipError_t launch_persistent_t(const KParams &p, int cols, int grid, hipStream_t stream) {
+    if (cols == 32)
+        hipLaunchKernelGGL((persistent_kernel<32, REV, NM>), dim3(grid), dim3(kWave), 0, stream, p);
+    else if (cols == 16)
+        hipLaunchKernelGGL((persistent_kernel<16, REV, NM>), dim3(grid), dim3(kWave), 0, stream, p);
+    else if (cols == 8)
+        hipLaunchKernelGGL((persistent_kernel<8, REV, NM>), dim3(grid), dim3(kWave), 0, stream, p);
+    else
+        return hipErrorInvalidValue;
     return hipGetLastError();
+}
+
+hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream) {
+    const bool nm = p.q_nmask || p.t_nmask;
+    if (p.in_score)
+        return nm ? launch_persistent_t<true, true>(p, cols, grid, stream)
+                  : launch_persistent_t<true, false>(p, cols, grid, stream);
+    return nm ? launch_persistent_t<false, true>(p, cols, grid, stream)
+              : launch_persistent_t<false, false>(p, cols, grid, stream);
 }
 
 }  // namespace salo

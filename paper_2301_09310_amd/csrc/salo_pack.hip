@@ -37,14 +37,27 @@ __device__ __forceinline__ uint32_t char_code(uint32_t c, bool &ok) {
 //   code     = ((c >> 1) ^ (c >> 2)) & 3 per byte (A/a 0, C/c 1, G/g 2, T/t 3)
 //   expected = "acgt"[code] per byte (one v_perm)
 //   a byte is valid iff (c | 0x20) == expected (exact per-byte zero test)
-template <bool RC>
-__device__ __forceinline__ uint32_t pack4(uint32_t x, uint32_t &bad) {
+// 0x80 in every byte of d that is zero (exact: no borrow between bytes)
+__device__ __forceinline__ uint32_t zero_bytes(uint32_t d) {
+    return ((((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u) ^ 0x80808080u;
+}
+
+// With NM, N and n are bases too: their code is 0 and bit b of `nbits`
+// (byte b) is set; without NM they are invalid like any other character.
+template <bool RC, bool NM = false>
+__device__ __forceinline__ uint32_t pack4(uint32_t x, uint32_t &bad, uint32_t *nbits = nullptr) {
     const uint32_t code = ((x >> 1) ^ (x >> 2)) & 0x03030303u;
     const uint32_t expect = __builtin_amdgcn_perm(0u, 0x74676361u, code);
-    const uint32_t d = (x | 0x20202020u) ^ expect;
-    const uint32_t nz = (((d & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | d) & 0x80808080u;
-    const uint32_t ok = nz ^ 0x80808080u;                  // 0x80 in valid bytes
-    bad += 4u - (uint32_t)__builtin_popcount(ok);
+    const uint32_t lo = x | 0x20202020u;
+    const uint32_t ok = zero_bytes(lo ^ expect);           // 0x80 in A/C/G/T bytes
+    if constexpr (NM) {
+        const uint32_t isn = zero_bytes(lo ^ 0x6E6E6E6Eu); // 0x80 in N/n bytes
+        *nbits = ((isn >> 7) & 1u) | ((isn >> 14) & 2u) | ((isn >> 21) & 4u) |
+                 ((isn >> 28) & 8u);
+        bad += 4u - (uint32_t)__builtin_popcount(ok | isn);
+    } else {
+        bad += 4u - (uint32_t)__builtin_popcount(ok);
+    }
     uint32_t c = RC ? (code ^ 0x03030303u) : code;
     c &= (ok >> 6) | (ok >> 7);                            // 0x03 in valid bytes
     return (c | (c >> 6) | (c >> 12) | (c >> 18)) & 0xFFu;
@@ -59,13 +72,25 @@ __device__ __forceinline__ void add_invalid(unsigned long long *invalid, uint32_
         atomicAdd(invalid, (unsigned long long)v);
 }
 
-template <bool V4>
+// N bits of 16 bases per thread: the even thread of each pair writes the
+// 32-bit mask word (its bits low, its neighbour's high).  Every thread of
+// the wave takes part in the exchange.
+__device__ __forceinline__ void store_nmask(uint32_t *n_mask, int64_t w, int64_t nw,
+                                            uint32_t nb16) {
+    const uint32_t hi = (uint32_t)__shfl_down((int)nb16, 1, 64);
+    if (w < nw && (w & 1) == 0) n_mask[w >> 1] = nb16 | (w + 1 < nw ? (hi << 16) : 0u);
+}
+
+__device__ __forceinline__ bool is_n_char(uint32_t c) { return (c | 0x20u) == 'n'; }
+
+template <bool V4, bool NM>
 __global__ __launch_bounds__(kPackThreads) void pack_forward(const uint8_t *chars, int64_t n,
-                                                             uint32_t *out,
+                                                             uint32_t *out, uint32_t *n_mask,
                                                              unsigned long long *invalid) {
     const int64_t w = (int64_t)blockIdx.x * kPackThreads + threadIdx.x;
     const int64_t nw = (n + 15) >> 4;
     uint32_t bad = 0;
+    uint32_t nb16 = 0;
     if (w < nw) {
         const int64_t p0 = w << 4;
         uint32_t word = 0;
@@ -80,17 +105,25 @@ __global__ __launch_bounds__(kPackThreads) void pack_forward(const uint8_t *char
                 for (int d = 0; d < 4; ++d) x[d] = src[d];
             }
 #pragma unroll
-            for (int d = 0; d < 4; ++d) word |= pack4<false>(x[d], bad) << (8 * d);
+            for (int d = 0; d < 4; ++d) {
+                uint32_t nb4 = 0;
+                word |= pack4<false, NM>(x[d], bad, &nb4) << (8 * d);
+                nb16 |= nb4 << (4 * d);
+            }
         } else {
             for (int k = 0; k < 16 && p0 + k < n; ++k) {
                 bool ok;
-                const uint32_t code = char_code(chars[p0 + k], ok);
-                bad += ok ? 0u : 1u;
+                const uint32_t c = chars[p0 + k];
+                const uint32_t code = char_code(c, ok);
+                const bool isn = NM && is_n_char(c);
+                bad += (ok || isn) ? 0u : 1u;
                 word |= (ok ? code : 0u) << (2 * k);
+                nb16 |= (isn ? 1u : 0u) << k;
             }
         }
         out[w] = word;
     }
+    if constexpr (NM) store_nmask(n_mask, w, nw, nb16);
     add_invalid(invalid, bad);
 }
 
@@ -139,9 +172,11 @@ __device__ __forceinline__ void seq_bounds(const int64_t *win, int64_t s0, const
     (void)n_seqs;
 }
 
+template <bool NM>
 __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *chars, int64_t n,
                                                              const int64_t *off,
                                                              int64_t n_seqs, uint32_t *out,
+                                                             uint32_t *n_mask,
                                                              unsigned long long *invalid) {
     __shared__ int64_t win[kWin + 1];
     __shared__ int64_t s_first;
@@ -162,6 +197,7 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
 
     const int64_t w = w0 + threadIdx.x;
     uint32_t bad = 0;
+    uint32_t nb16 = 0;
     if (w < nw) {
         const int64_t p0 = w << 4;
         uint32_t word = 0;
@@ -220,7 +256,9 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
 #pragma unroll
                     for (int q = 0; q < 4; ++q) {
                         const uint32_t rev = __builtin_amdgcn_perm(0u, g[3 - q], 0x00010203u);
-                        word |= pack4<true>(rev, bad) << (8 * q);
+                        uint32_t nb4 = 0;
+                        word |= pack4<true, NM>(rev, bad, &nb4) << (8 * q);
+                        nb16 |= nb4 << (4 * q);
                     }
                 }
             }
@@ -229,6 +267,7 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
             // per base: tails, words spanning three or more sequences, and
             // offsets that break the documented rule
             word = 0;
+            nb16 = 0;
             int64_t sc = s;
             for (int k = 0; k < 16; ++k) {
                 const int64_t p = p0 + k;
@@ -239,41 +278,58 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
                     ++sc;
                     seq_bounds(win, s0, off, n_seqs, sc, lo, hi);
                 }
-                bool ok = false;
+                bool ok = false, isn = false;
                 uint32_t code = 0;
                 if (sc >= 0 && sc < n_seqs && lo <= p && p < hi) {
                     const int64_t src = lo + hi - 1 - p;
-                    if (src >= 0 && src < n) code = 3u - char_code(chars[src], ok);
+                    if (src >= 0 && src < n) {
+                        const uint32_t c = chars[src];
+                        code = 3u - char_code(c, ok);
+                        isn = NM && is_n_char(c);
+                    }
                 }
-                bad += ok ? 0u : 1u;
+                bad += (ok || isn) ? 0u : 1u;
                 word |= (ok ? code : 0u) << (2 * k);
+                nb16 |= (isn ? 1u : 0u) << k;
             }
         }
         out[w] = word;
     }
+    if constexpr (NM) store_nmask(n_mask, w, nw, nb16);
     add_invalid(invalid, bad);
 }
 
 }  // namespace
 
-hipError_t launch_pack(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
-                       int64_t n_seqs, bool revcomp, uint8_t *packed,
-                       unsigned long long *invalid, hipStream_t stream) {
+template <bool NM>
+hipError_t launch_pack_t(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
+                         int64_t n_seqs, bool revcomp, uint8_t *packed, uint32_t *n_mask,
+                         unsigned long long *invalid, hipStream_t stream) {
     const int64_t nw = (n_chars + 15) >> 4;
     const int64_t blocks = (nw + kPackThreads - 1) / kPackThreads;
     if (blocks <= 0) return hipSuccess;
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
     uint32_t *out = reinterpret_cast<uint32_t *>(packed);
     if (revcomp)
-        hipLaunchKernelGGL(pack_revcomp, dim3((uint32_t)blocks), dim3(kPackThreads), 0, stream,
-                           chars, n_chars, offsets, n_seqs, out, invalid);
+        hipLaunchKernelGGL((pack_revcomp<NM>), dim3((uint32_t)blocks), dim3(kPackThreads), 0,
+                           stream, chars, n_chars, offsets, n_seqs, out, n_mask, invalid);
     else if ((reinterpret_cast<uintptr_t>(chars) & 15) == 0)
-        hipLaunchKernelGGL((pack_forward<true>), dim3((uint32_t)blocks), dim3(kPackThreads), 0,
-                           stream, chars, n_chars, out, invalid);
+        hipLaunchKernelGGL((pack_forward<true, NM>), dim3((uint32_t)blocks), dim3(kPackThreads),
+                           0, stream, chars, n_chars, out, n_mask, invalid);
     else
-        hipLaunchKernelGGL((pack_forward<false>), dim3((uint32_t)blocks), dim3(kPackThreads), 0,
-                           stream, chars, n_chars, out, invalid);
+        hipLaunchKernelGGL((pack_forward<false, NM>), dim3((uint32_t)blocks), dim3(kPackThreads),
+                           0, stream, chars, n_chars, out, n_mask, invalid);
     return hipGetLastError();
+}
+
+hipError_t launch_pack(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
+                       int64_t n_seqs, bool revcomp, uint8_t *packed, uint32_t *n_mask,
+                       unsigned long long *invalid, hipStream_t stream) {
+    if (n_mask)
+        return launch_pack_t<true>(chars, n_chars, offsets, n_seqs, revcomp, packed, n_mask,
+                                   invalid, stream);
+    return launch_pack_t<false>(chars, n_chars, offsets, n_seqs, revcomp, packed, nullptr,
+                                invalid, stream);
 }
 
 }  // namespace salo

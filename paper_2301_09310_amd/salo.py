@@ -81,10 +81,13 @@ def load(path: str | None = None):
         lib.salo_get_bins.restype = i32
         lib.salo_version.argtypes = []
         lib.salo_version.restype = i32
-        lib.salo_align_starts.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp,
-                                          vp, ctypes.POINTER(Options)]
+        lib.salo_align_starts.argtypes = [vp, vp, vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp,
+                                          vp, vp, ctypes.POINTER(Options)]
         lib.salo_align_starts.restype = i32
-        lib.salo_pack_bases.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp]
+        lib.salo_pack_bases.argtypes = [vp, i64, vp, i64, i32, vp, vp, vp, vp]
+        lib.salo_align_batch_n.argtypes = [vp, vp, vp, vp, vp, vp, i64, Scoring, vp, vp, vp,
+                                           vp, ctypes.POINTER(Options)]
+        lib.salo_align_batch_n.restype = i32
         lib.salo_pack_bases.restype = i32
         if path is None:
             _lib = lib
@@ -115,13 +118,25 @@ def make_options(mode="auto", lanes=0, cols=0, force_int32=False, waves_per_cu=0
     return o
 
 
+def _mask_arg(mask, name):
+    import torch
+    if mask is None:
+        return None
+    if not mask.is_cuda or mask.dtype not in (torch.int32, torch.uint32) or \
+            not mask.is_contiguous():
+        raise ValueError("%s must be a contiguous 32-bit CUDA tensor" % name)
+    return mask.data_ptr()
+
+
 def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
-                out=None, stream=None, **options):
+                out=None, stream=None, q_nmask=None, t_nmask=None, **options):
     """Align every pair on the GPU.
 
     q_seqs/t_seqs: uint8 CUDA tensors (2-bit packed); q_offsets/t_offsets:
     int64 CUDA tensors of n_pairs+1 entries.  Returns (score, q_end, t_end)
-    int32 CUDA tensors (or fills `out`, a triple of such tensors).  Keyword
+    int32 CUDA tensors (or fills `out`, a triple of such tensors).
+    q_nmask / t_nmask: optional int32 CUDA tensors, one bit per base marking
+    N (salo_align_batch_n).  Keyword
     options: mode ('auto' | 'plain' | 'persistent'), lanes, cols,
     force_int32, no_f16, waves_per_cu, timing.
     """
@@ -140,16 +155,23 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
         out = tuple(torch.empty(max(n, 0), dtype=torch.int32, device=dev) for _ in range(3))
     sc = Scoring(*[int(x) for x in scoring])
     opts = make_options(**options)
-    st = lib.salo_align_batch_ex(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
-                                 t_offsets.data_ptr(), n, sc, out[0].data_ptr(),
-                                 out[1].data_ptr(), out[2].data_ptr(),
-                                 _stream_handle(stream), ctypes.byref(opts))
+    qm, tm = _mask_arg(q_nmask, "q_nmask"), _mask_arg(t_nmask, "t_nmask")
+    if qm is None and tm is None:
+        st = lib.salo_align_batch_ex(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                                     t_offsets.data_ptr(), n, sc, out[0].data_ptr(),
+                                     out[1].data_ptr(), out[2].data_ptr(),
+                                     _stream_handle(stream), ctypes.byref(opts))
+    else:
+        st = lib.salo_align_batch_n(q_seqs.data_ptr(), qm, q_offsets.data_ptr(),
+                                    t_seqs.data_ptr(), tm, t_offsets.data_ptr(), n, sc,
+                                    out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
+                                    _stream_handle(stream), ctypes.byref(opts))
     _check(lib, st)
     return out
 
 
 def align_starts(q_seqs, q_offsets, t_seqs, t_offsets, answers, scoring=(1, -4, 6, 1),
-                 out=None, stream=None, **options):
+                 out=None, stream=None, q_nmask=None, t_nmask=None, **options):
     """Start positions of the align call's answers (salo_align_starts).
     answers: the (score, q_end, t_end) int32 CUDA tensors of align_batch on
     the same inputs and scoring.  Returns (q_start, t_start) int32 CUDA
@@ -165,8 +187,10 @@ def align_starts(q_seqs, q_offsets, t_seqs, t_offsets, answers, scoring=(1, -4, 
         out = tuple(torch.empty(max(n, 0), dtype=torch.int32, device=dev) for _ in range(2))
     sc = Scoring(*[int(x) for x in scoring])
     opts = make_options(**options)
-    st = lib.salo_align_starts(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
-                               t_offsets.data_ptr(), n, sc, answers[0].data_ptr(),
+    st = lib.salo_align_starts(q_seqs.data_ptr(), _mask_arg(q_nmask, "q_nmask"),
+                               q_offsets.data_ptr(), t_seqs.data_ptr(),
+                               _mask_arg(t_nmask, "t_nmask"), t_offsets.data_ptr(), n, sc,
+                               answers[0].data_ptr(),
                                answers[1].data_ptr(), answers[2].data_ptr(), out[0].data_ptr(),
                                out[1].data_ptr(), _stream_handle(stream), ctypes.byref(opts))
     _check(lib, st)
@@ -220,12 +244,14 @@ def load_tune_table(path: str) -> None:
 
 
 def pack_bases(chars, offsets=None, revcomp: bool = False, out=None, invalid=None,
-               stream=None):
+               stream=None, n_mask=None):
     """Pack character reads on the GPU (salo_pack_bases).  chars: uint8
     CUDA tensor; offsets: int64 CUDA tensor (sequence CSR, needed for
     revcomp).  Returns the packed uint8 CUDA tensor of ceil(n/16)*4 bytes
     (or fills `out`).  `invalid`, if given, is an int64 CUDA tensor of one
-    element to which the number of invalid bases is added."""
+    element to which the number of invalid bases is added.  `n_mask`, if
+    given, is an int32 CUDA tensor of ceil(n/32) words that receives the N
+    bits (N and n then count as bases)."""
     import torch
     lib = load()
     if not chars.is_cuda or chars.dtype != torch.uint8 or not chars.is_contiguous():
@@ -248,8 +274,14 @@ def pack_bases(chars, offsets=None, revcomp: bool = False, out=None, invalid=Non
         if not invalid.is_cuda or invalid.dtype != torch.int64:
             raise ValueError("invalid must be an int64 CUDA tensor")
         inv_ptr = invalid.data_ptr()
+    nm_ptr = None
+    if n_mask is not None:
+        if n_mask.numel() < (n + 31) // 32:
+            raise ValueError("n_mask holds %d words, %d needed" % (n_mask.numel(),
+                                                                  (n + 31) // 32))
+        nm_ptr = _mask_arg(n_mask, "n_mask")
     st = lib.salo_pack_bases(chars.data_ptr() if n else None, n, off_ptr, n_seqs,
-                             1 if revcomp else 0, out.data_ptr(), inv_ptr,
+                             1 if revcomp else 0, out.data_ptr(), nm_ptr, inv_ptr,
                              _stream_handle(stream))
     _check(lib, st)
     return out

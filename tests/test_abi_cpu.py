@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
               "salo_error_count", "salo_last_timing", "salo_set_bins", "salo_get_bins",
               "salo_last_error", "salo_release", "salo_version", "salo_pack_bases",
-              "salo_align_starts"]:
+              "salo_align_starts", "salo_align_batch_n"]:
         assert n in names
 
 
@@ -120,8 +120,8 @@ def test_bad_bin_tables(lib, table):
     assert salo.get_bins() == before
 
 
-def _pack(n, chars=ADDR, off=ADDR, n_seqs=1, revcomp=0, packed=ADDR, inv=None):
-    return salo.load().salo_pack_bases(chars, n, off, n_seqs, revcomp, packed, inv, NULL)
+def _pack(n, chars=ADDR, off=ADDR, n_seqs=1, revcomp=0, packed=ADDR, inv=None, nmask=None):
+    return salo.load().salo_pack_bases(chars, n, off, n_seqs, revcomp, packed, nmask, inv, NULL)
 
 
 def test_pack_validation(lib):
@@ -138,12 +138,13 @@ def test_pack_validation(lib):
     assert _pack(16, packed=ADDR + 2) == -1
     assert _pack(16, off=ADDR + 4, revcomp=1) == -1
     assert _pack(16, inv=ADDR + 4) == -1
+    assert _pack(16, nmask=ADDR + 2) == -1
 
 
-def _starts(n, ptr=ADDR, ans=ADDR, opts=None):
+def _starts(n, ptr=ADDR, ans=ADDR, opts=None, mask=None):
     o = opts if opts is not None else salo.make_options()
-    return salo.load().salo_align_starts(ptr, ptr, ptr, ptr, n, SC, ans, ans, ans, ptr, ptr,
-                                         NULL, ctypes.byref(o))
+    return salo.load().salo_align_starts(ptr, mask, ptr, ptr, mask, ptr, n, SC, ans, ans, ans,
+                                         ptr, ptr, NULL, ctypes.byref(o))
 
 
 def test_starts_validation(lib):
@@ -152,6 +153,19 @@ def test_starts_validation(lib):
     assert _starts(5, ans=None) == -1
     assert _starts(5, ans=ADDR + 2) == -1
     assert _starts(5, ptr=ADDR + 1) == -1
+    assert _starts(5, mask=ADDR + 1) == -1
     o = salo.make_options(mode="plain")
     assert _starts(5, opts=o) == -5
     assert "persistent" in lib.salo_last_error().decode()
+
+
+def test_masked_align_validation(lib):
+    o = salo.make_options()
+    f = salo.load().salo_align_batch_n
+    assert f(None, None, None, None, None, None, 0, SC, None, None, None, NULL,
+             ctypes.byref(o)) == 0
+    assert f(ADDR, ADDR + 2, ADDR, ADDR, None, ADDR, 5, SC, ADDR, ADDR, ADDR, NULL,
+             ctypes.byref(o)) == -1
+    assert "mask" in lib.salo_last_error().decode()
+    assert f(ADDR, None, ADDR, ADDR, None, ADDR, -1, SC, ADDR, ADDR, ADDR, NULL,
+             ctypes.byref(o)) == -1
