@@ -37,14 +37,34 @@ PEAK_TOPS["f16x2"] = PEAK_TOPS["f16x2+u16x2"] = PEAK_TOPS["u16x2"]   # packed 16
 HBM_PEAK_GBS = 8000.0
 
 
-def cell_dtype(batch, scoring=SCORING) -> str:
+def subset_masks(batch, idx, masks):
+    """N masks of batch.subset(idx): the sampled pairs' bits, in the
+    subset's stream layout."""
+    out = []
+    for mask, off in zip(masks, (batch.q_offsets, batch.t_offsets)):
+        if mask is None:
+            out.append(None)
+            continue
+        bits = np.unpackbits(mask.view(np.uint8), bitorder="little")
+        parts = [bits[off[p]:off[p + 1]] for p in idx]
+        sel = np.concatenate(parts) if parts else np.zeros(0, np.uint8)
+        words = np.zeros(max((sel.size + 31) // 32, 1), np.uint32)
+        packed = np.packbits(sel, bitorder="little")
+        words.view(np.uint8)[: packed.size] = packed
+        out.append(words)
+    return out
+
+
+def cell_dtype(batch, scoring=SCORING, n_masks=False) -> str:
     """Cell arithmetic the library picks for this batch: binary16 where a
     pair's best score is at most 2048 (the scoring fits the binary16 row
     table), 16-bit integers elsewhere (32-bit beyond the 16-bit bound)."""
     match, mism = scoring[0], scoring[1]
     mn = np.minimum(batch.q_lens(), batch.t_lens())
-    half = match * mn <= 2048
+    half = (match * mn <= 2048) & (not n_masks)
     u16 = match * (mn + 1) - mism <= 0x7BFF
+    if n_masks and u16.all():
+        return "u16x2"
     if half.all():
         return "f16x2"
     if (half | u16).all():
@@ -113,6 +133,9 @@ def main(argv=None) -> int:
                     help="only run 3 device-to-device copies of BYTES bytes (a known-"
                          "traffic kernel for scaling the profiler's byte counters)")
     ap.add_argument("--plain-lanes", type=int, default=4)
+    ap.add_argument("--n-fraction", type=float, default=0.0,
+                    help="mark this fraction of bases (both streams, seeded) as N and "
+                         "align through the N-mask entry point")
     ap.add_argument("--starts", action="store_true",
                     help="also time the start-position pass on the timed step's answers")
     ap.add_argument("--pack", action="store_true",
@@ -169,9 +192,25 @@ def main(argv=None) -> int:
 
     q, qo, t, to = salo.to_device(batch, dev)
     n = batch.n_pairs
+    q_nmask = t_nmask = None
+    masks_np = (None, None)
+    if args.n_fraction > 0:
+        rng_n = np.random.default_rng([0, 99])
+
+        def n_mask(total):
+            bits = rng_n.random(total) < args.n_fraction
+            words = np.zeros(max((total + 31) // 32, 1), np.uint32)
+            idx = np.nonzero(bits)[0]
+            np.bitwise_or.at(words, idx >> 5, np.uint32(1) << (idx & 31).astype(np.uint32))
+            return words
+        masks_np = (n_mask(int(batch.q_offsets[-1])), n_mask(int(batch.t_offsets[-1])))
+        q_nmask = torch.from_numpy(masks_np[0].view(np.int32)).to(dev)
+        t_nmask = torch.from_numpy(masks_np[1].view(np.int32)).to(dev)
     out = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(3))
     opts = dict(mode=args.mode, lanes=args.lanes, cols=args.cols,
                 waves_per_cu=args.waves_per_cu)
+    if q_nmask is not None:
+        opts.update(q_nmask=q_nmask, t_nmask=t_nmask)
     stream = torch.cuda.current_stream()
 
     for _ in range(args.warmup):
@@ -227,6 +266,8 @@ def main(argv=None) -> int:
     if args.compare_plain and args.mode != "plain":
         popts = dict(mode="plain", lanes=args.plain_lanes, cols=16,
                      waves_per_cu=args.waves_per_cu)
+        if q_nmask is not None:
+            popts.update(q_nmask=q_nmask, t_nmask=t_nmask)
         t_first = time.perf_counter()
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
         torch.cuda.synchronize()
@@ -280,10 +321,11 @@ def main(argv=None) -> int:
         k_s = min(args.parity_sample, n)
         idx_s = np.sort(rng_s.choice(n, size=k_s, replace=False))
         sub_s = batch.subset(idx_s)
+        smq, smt = subset_masks(batch, idx_s, masks_np)
         w_ans = O.align_batch(sub_s.q_seqs, sub_s.q_offsets, sub_s.t_seqs, sub_s.t_offsets,
-                              SCORING)
+                              SCORING, q_nmask=smq, t_nmask=smt)
         w_st = O.start_batch(sub_s.q_seqs, sub_s.q_offsets, sub_s.t_seqs, sub_s.t_offsets,
-                             *w_ans, scoring=SCORING)
+                             *w_ans, scoring=SCORING, q_nmask=smq, t_nmask=smt)
         ok_s = all(np.array_equal(g.cpu().numpy()[idx_s].astype(np.int64), w)
                    for g, w in zip(sq, w_st))
         starts = {"ms_per_step": round(s_ms, 4), "dp_ms": round(float(np.mean(s_dp)), 4),
@@ -299,12 +341,14 @@ def main(argv=None) -> int:
     idx = np.sort(rng.choice(n, size=k, replace=False))
     got = [x.cpu().numpy()[idx].astype(np.int64) for x in out]
     sub = batch.subset(idx)
-    want = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING)
+    sqm, stm = subset_masks(batch, idx, masks_np)
+    want = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING,
+                         q_nmask=sqm, t_nmask=stm)
     parity_ok = all(np.array_equal(g, w) for g, w in zip(got, want))
     log("parity on %d sampled pairs: %s" % (k, "bit-exact" if parity_ok else "MISMATCH"))
 
     # roofline of the DP kernel: algorithmic int ops per launch / launch time
-    dtype = cell_dtype(batch)
+    dtype = cell_dtype(batch, n_masks=q_nmask is not None)
     kern_ms = float(np.mean(dp_ms))
     achieved = OPS_PER_CELL * cells / (kern_ms * 1e-3) / 1e12
     peak = PEAK_TOPS[dtype]
@@ -319,10 +363,11 @@ def main(argv=None) -> int:
     if not args.no_cpu_baseline:
         m = min(args.cpu_sample, n)
         sub = batch.subset(np.arange(m))
+        cmq, cmt = subset_masks(batch, np.arange(m), masks_np)
         thr = O.default_threads()
         c0 = time.perf_counter()
         O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING,
-                      nthreads=thr)
+                      nthreads=thr, q_nmask=cmq, t_nmask=cmt)
         dt = time.perf_counter() - c0
         cpu = {"value": round(sub.cells() / dt / 1e9, 4), "unit": "GCUPS", "cores": thr,
                "kind": "oracle",
@@ -339,6 +384,7 @@ def main(argv=None) -> int:
                    "cols": args.cols, "parity": "bit-exact on %d sampled pairs" % k
                    if parity_ok else "MISMATCH on sampled pairs",
                    "plan_ms": round(float(np.mean(plan_ms)), 4), "graph": bool(args.graph),
+                   "n_fraction": args.n_fraction,
                    "dp_ms": round(kern_ms, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
