@@ -8,7 +8,10 @@ It wraps ``gotoh_oracle.c``: a plain scalar int64 implementation of the
 SALoBa paper's Eq. 1 (Section II-A), the affine-gap Smith-Waterman-Gotoh
 recurrence, returning per pair the highest cell score and its end position
 (first maximum in row-major order over target rows and query columns; see
-the header of the C file for every reading of the paper it takes).
+the header of the C file for every reading of the paper it takes), and the
+companion files: ``pack_oracle.c`` (2-bit packing and reverse complement),
+``start_oracle.c`` (start positions of the best alignment) and
+``band_oracle.c`` (Eq. 1 restricted to a diagonal band, Section VII-B).
 
 The shared library is compiled from the C source with gcc on first use
 (and by the repository's build step); it has no dependency on the GPU code.
@@ -24,7 +27,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gotoh_oracle.c")
-_SRCS = [_SRC, os.path.join(_HERE, "pack_oracle.c"), os.path.join(_HERE, "start_oracle.c")]
+_SRCS = [_SRC, os.path.join(_HERE, "pack_oracle.c"), os.path.join(_HERE, "start_oracle.c"),
+         os.path.join(_HERE, "band_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle_gotoh.so")
 _lock = threading.Lock()
 _lib = None
@@ -67,6 +71,9 @@ def _load():
             lib.oracle_start_batch_n.argtypes = [p, p, p, p, p, p, i64, i64, i64, i64, i64,
                                                  p, p, p, p, p]
             lib.oracle_start_batch_n.restype = i64
+            lib.oracle_align_banded.argtypes = [p, p, p, p, i64, i64, i64, i64, i64, i64,
+                                                p, p, p]
+            lib.oracle_align_banded.restype = ctypes.c_int
             lib.oracle_start_batch.argtypes = [p, p, p, p, i64, i64, i64, i64, i64,
                                                p, p, p, p, p]
             lib.oracle_start_batch.restype = i64
@@ -223,3 +230,27 @@ def start_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_end, t_end,
     if bad != 0:
         raise RuntimeError("start oracle: %d pairs whose anchored maximum is not the score" % bad)
     return qs, ts
+
+
+def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4, 6, 1)):
+    """Oracle of Eq. 1 restricted to the band |i - j| <= band (see the header
+    of band_oracle.c).  Returns (score, q_end, t_end) int64 arrays."""
+    if band < 0:
+        raise ValueError("band must be >= 0")
+    lib = _load()
+    n = len(q_offsets) - 1
+    out = [np.zeros(max(n, 0), np.int64) for _ in range(3)]
+    if n <= 0:
+        return tuple(out)
+    q_seqs = np.ascontiguousarray(q_seqs, dtype=np.uint8)
+    t_seqs = np.ascontiguousarray(t_seqs, dtype=np.uint8)
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.int64)
+    t_offsets = np.ascontiguousarray(t_offsets, dtype=np.int64)
+    qb = q_seqs if len(q_seqs) else np.zeros(1, np.uint8)
+    tb = t_seqs if len(t_seqs) else np.zeros(1, np.uint8)
+    a, b, o, e = (int(x) for x in scoring)
+    rc = lib.oracle_align_banded(_ptr(qb), _ptr(q_offsets), _ptr(tb), _ptr(t_offsets), n,
+                                 a, b, o, e, int(band), *(_ptr(x) for x in out))
+    if rc != 0:
+        raise MemoryError("oracle_align_banded failed")
+    return tuple(out)

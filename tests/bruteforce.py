@@ -30,8 +30,10 @@ def _s(tb, qb, a, b):
     return a if tb == qb and tb != "N" else b
 
 
-def enumerate_h(q, t, scoring):
-    """H table (list of rows over t, columns over q) by exhaustive search."""
+def enumerate_h(q, t, scoring, band=None):
+    """H table (list of rows over t, columns over q) by exhaustive search.
+    With band=w, only paths whose every cell (last consumed target base,
+    last consumed query base) satisfies |i - j| <= w are counted."""
     a, b, o, e = scoring
     m, n = len(q), len(t)
     H = [[0] * m for _ in range(n)]
@@ -41,6 +43,8 @@ def enumerate_h(q, t, scoring):
         # (i, j): next target / query base to consume
         if used_t and used_q:
             ti, qj = i - 1, j - 1
+            if band is not None and abs(ti - qj) > band:
+                return
             if score > H[ti][qj]:
                 H[ti][qj] = score
         if i < n and j < m:
