@@ -105,7 +105,8 @@ def main(argv=None) -> int:
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="short_reads")
+    ap.add_argument("--workload", default=None,
+                    help="default short_reads (anchored_long with --band)")
     ap.add_argument("--pairs", type=int, default=0, help="override the pair count")
     ap.add_argument("--mode", default="auto")
     ap.add_argument("--lanes", type=int, default=0)
@@ -138,10 +139,14 @@ def main(argv=None) -> int:
                          "align through the N-mask entry point")
     ap.add_argument("--starts", action="store_true",
                     help="also time the start-position pass on the timed step's answers")
+    ap.add_argument("--band", type=int, default=-1, metavar="W",
+                    help="time the banded pass (cells with |i - j| <= W) instead")
     ap.add_argument("--pack", action="store_true",
                     help="time the on-device packing of the workload's reads written as "
                          "characters (forward and reverse-complement)")
     args = ap.parse_args(argv)
+    if args.workload is None:
+        args.workload = "anchored_long" if args.band >= 0 else "short_reads"
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -173,6 +178,8 @@ def main(argv=None) -> int:
         return serve_bench(args)
     if args.pack:
         return pack_bench(args)
+    if args.band >= 0:
+        return band_bench(args)
 
     gen = I.WORKLOADS[args.workload]
     t0 = time.time()
@@ -393,6 +400,129 @@ def main(argv=None) -> int:
     }
     print(json.dumps(rec), flush=True)
     return 0 if parity_ok and (starts is None or starts["parity"] != "MISMATCH") else 1
+
+
+def band_bench(args) -> int:
+    """GCUPS of salo_align_batch_banded over the cells inside the band
+    (|i - j| <= W; Section VII-B) on the anchored long workload, with the
+    unbanded pass on the same batch for comparison, parity on sampled pairs
+    against the banded oracle, the roofline of the DP kernel over the band's
+    cells, and the banded oracle timed on the host."""
+    import torch
+    from oracle import oracle as O
+    from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import salo
+    dev = torch.device("cuda:0")
+    w = args.band
+    gen = I.WORKLOADS[args.workload]
+    t0 = time.time()
+    batch = gen(0, args.pairs) if args.pairs else gen(0)
+    n = batch.n_pairs
+    rect = batch.cells()
+    bcells = int(I.band_cells(batch.q_lens(), batch.t_lens(), w).sum())
+    log("workload %s: %d pairs, %.3e cells, %.3e in the band %d, generated in %.1fs" % (
+        args.workload, n, rect, bcells, w, time.time() - t0))
+    q, qo, t, to = salo.to_device(batch, dev)
+    out = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(3))
+    opts = dict(lanes=args.lanes, cols=args.cols, waves_per_cu=args.waves_per_cu)
+    stream = torch.cuda.current_stream()
+    for _ in range(max(args.warmup, 1)):
+        salo.align_banded(q, qo, t, to, w, SCORING, out=out, stream=stream, **opts)
+    torch.cuda.synchronize()
+    log("banded warm-up done")
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    plan_ms, dp_ms = [], []
+    ev0.record(stream)
+    for _ in range(args.steps):
+        salo.align_banded(q, qo, t, to, w, SCORING, out=out, stream=stream, timing=True,
+                          **opts)
+        a, b = salo.last_timing(stream)
+        plan_ms.append(a)
+        dp_ms.append(b)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    gcups = bcells / (ms * 1e-3) / 1e9
+    log("banded: %.3f ms per step (DP %s), %.1f GCUPS over band cells"
+        % (ms, " ".join("%.2f" % x for x in dp_ms), gcups))
+    assert salo.error_count(stream) == 0
+
+    # the unbanded pass on the same batch
+    full = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(3))
+    salo.align_batch(q, qo, t, to, SCORING, out=full, stream=stream)
+    torch.cuda.synchronize()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(args.steps):
+        salo.align_batch(q, qo, t, to, SCORING, out=full, stream=stream)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    fms = e0.elapsed_time(e1) / args.steps
+    g_np = [x.cpu().numpy().astype(np.int64) for x in out]
+    f_np = [x.cpu().numpy().astype(np.int64) for x in full]
+    same = float(np.mean((g_np[0] == f_np[0]) & (g_np[1] == f_np[1]) & (g_np[2] == f_np[2])))
+    log("unbanded: %.3f ms per step; banded answer = unbanded answer for %.4f of pairs"
+        % (fms, same))
+
+    rng = np.random.default_rng(1)
+    k = min(args.parity_sample, n, 300)
+    idx = np.sort(rng.choice(n, size=k, replace=False))
+    sub = batch.subset(idx)
+    want = O.align_banded(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, w, SCORING)
+    parity_ok = all(np.array_equal(g[idx], x) for g, x in zip(g_np, want))
+    log("parity on %d sampled pairs: %s" % (k, "bit-exact" if parity_ok else "MISMATCH"))
+
+    dtype = cell_dtype(batch)
+    kern_ms = float(np.mean(dp_ms))
+    achieved = OPS_PER_CELL * bcells / (kern_ms * 1e-3) / 1e12
+    peak = PEAK_TOPS[dtype]
+    wl = "%s_band%d" % (args.workload, w)
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic(wl), "kernel": "persistent_kernel (banded)",
+            "kernel_ms": round(kern_ms, 4), "ops_per_cell": OPS_PER_CELL,
+            "cells": "inside the band", "traffic_unit": "bytes per launch",
+            "kernel_source": kernel_source_hash()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = min(args.cpu_sample, n, 40000)
+        csub = batch.subset(np.arange(m))
+        thr = O.default_threads()
+        c0 = time.perf_counter()
+        O.align_banded(csub.q_seqs, csub.q_offsets, csub.t_seqs, csub.t_offsets, w, SCORING,
+                       threads=thr)
+        dt = time.perf_counter() - c0
+        cb = int(I.band_cells(csub.q_lens(), csub.t_lens(), w).sum())
+        cpu = {"value": round(cb / dt / 1e9, 4), "unit": "GCUPS over band cells",
+               "cores": thr, "kind": "oracle",
+               "sample": "first %d pairs of the %s batch (%.3e band cells; the oracle "
+                         "visits all %.3e cells of their tables), %.1fs" % (
+                             m, args.workload, cb, csub.cells(), dt)}
+        log("cpu oracle: %.3f GCUPS over band cells on %d threads" % (cpu["value"], thr))
+
+    rec = {
+        "metric": "GCUPS over the cells inside the band (bit-exact vs oracle), banded pass",
+        "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": n, "band": w, "band_cells": bcells,
+                   "table_cells": rect, "scoring": list(SCORING), "lanes": args.lanes,
+                   "cols": args.cols, "dp_ms": round(kern_ms, 4),
+                   "plan_ms": round(float(np.mean(plan_ms)), 4),
+                   "parity": "bit-exact on %d sampled pairs" % k
+                   if parity_ok else "MISMATCH on sampled pairs"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "comparison": {"unbanded_ms_per_step": round(fms, 4),
+                       "unbanded_gcups_table_cells": round(rect / (fms * 1e-3) / 1e9, 2),
+                       "speedup_vs_unbanded": round(fms / ms, 3),
+                       "pairs_with_unbanded_answer": round(same, 4)},
+    }
+    print(json.dumps(rec), flush=True)
+    return 0 if parity_ok else 1
 
 
 def pack_bench(args) -> int:

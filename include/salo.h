@@ -184,6 +184,29 @@ salo_status_t salo_align_starts(const uint8_t *q_seqs, const uint32_t *q_nmask,
                                 int32_t *out_qstart, int32_t *out_tstart, hipStream_t stream,
                                 const salo_options_t *opts);
 
+/*
+ * Banded alignment (Section VII-B: seed extension often fills only the
+ * cells within a fixed distance of the main diagonal).  Eq. 1 over the
+ * cells with |i - j| <= band only, i indexing target bases and j query
+ * bases; a cell outside the band acts as the table's boundary (H = 0, no
+ * gap open from it) and is never the answer.  Outputs as
+ * salo_align_batch: the highest in-band score and the first (row-major)
+ * in-band cell holding it; (0, -1, -1) when no in-band cell scores above
+ * 0.  A band of at least max(query, target length) - 1 gives
+ * salo_align_batch's answer.
+ * band: 0..65535 (else SALO_ERR_INVALID).  Other arguments, options and
+ * errors as salo_align_batch_ex; runs the persistent mode
+ * (opts->mode = SALO_MODE_PLAIN returns SALO_ERR_UNSUPPORTED).  With
+ * opts->lanes = 0 the lane-group width is chosen from the band: the
+ * largest power of two W with W * cols <= band / 2 (at least 1).
+ */
+salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                      const uint8_t *t_seqs, const int64_t *t_offsets,
+                                      int64_t n_pairs, salo_scoring_t scoring, int32_t band,
+                                      int32_t *out_score, int32_t *out_qend,
+                                      int32_t *out_tend, hipStream_t stream,
+                                      const salo_options_t *opts);
+
 /* Pre-size the workspace of (current device, stream) for batches of up to
  * max_pairs pairs, so later calls allocate nothing (needed before graph
  * capture).  Synchronous with respect to the host. */

@@ -232,7 +232,8 @@ def start_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_end, t_end,
     return qs, ts
 
 
-def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4, 6, 1)):
+def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4, 6, 1),
+                 threads: int | None = None):
     """Oracle of Eq. 1 restricted to the band |i - j| <= band (see the header
     of band_oracle.c).  Returns (score, q_end, t_end) int64 arrays."""
     if band < 0:
@@ -249,8 +250,24 @@ def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4
     qb = q_seqs if len(q_seqs) else np.zeros(1, np.uint8)
     tb = t_seqs if len(t_seqs) else np.zeros(1, np.uint8)
     a, b, o, e = (int(x) for x in scoring)
-    rc = lib.oracle_align_banded(_ptr(qb), _ptr(q_offsets), _ptr(tb), _ptr(t_offsets), n,
-                                 a, b, o, e, int(band), *(_ptr(x) for x in out))
-    if rc != 0:
+    # independent pairs: contiguous ranges on worker threads (ctypes
+    # releases the GIL for the call)
+    workers = max(1, min(threads or os.cpu_count() or 1, n))
+    cuts = np.linspace(0, n, workers + 1).astype(np.int64)
+
+    def run(k):
+        lo, hi = int(cuts[k]), int(cuts[k + 1])
+        if hi <= lo:
+            return 0
+        return lib.oracle_align_banded(_ptr(qb), _ptr(q_offsets) + 8 * lo, _ptr(tb),
+                                       _ptr(t_offsets) + 8 * lo, hi - lo, a, b, o, e, int(band),
+                                       *(_ptr(x) + 8 * lo for x in out))
+    if workers == 1:
+        rcs = [run(0)]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            rcs = list(ex.map(run, range(workers)))
+    if any(rc != 0 for rc in rcs):
         raise MemoryError("oracle_align_banded failed")
     return tuple(out)

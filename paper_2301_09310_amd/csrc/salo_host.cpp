@@ -200,11 +200,21 @@ struct NMasks {
     const uint32_t *q, *t;   // either may be nullptr
 };
 
+// Lanes per pair group of the banded pass: chunks of about w/2 columns.
+// A chunk of W*K columns runs W*K + 2w rows (plus the W-1 step ramp) to
+// cover its (2w+1)-wide stripe of the band, so narrow chunks waste fewer
+// cells; the boundary column written per chunk bounds how narrow they go.
+int band_lanes(int32_t band, int cols) {
+    int w = 1;
+    while (w < 64 && (int64_t)2 * w * 2 * cols <= band) w <<= 1;
+    return w;
+}
+
 salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
                         const uint8_t *t_seqs, const int64_t *t_offsets, int64_t n_pairs,
                         salo_scoring_t scoring, int32_t *out_score, int32_t *out_qend,
                         int32_t *out_tend, hipStream_t stream, const salo_options_t *opts,
-                        const StartArgs *starts, NMasks masks) {
+                        const StartArgs *starts, NMasks masks, int32_t band = -1) {
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
@@ -216,6 +226,8 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
         return fail(SALO_ERR_INVALID, "waves_per_cu must be in [0, 32]");
     if (starts && o.mode == SALO_MODE_PLAIN)
         return fail(SALO_ERR_UNSUPPORTED, "the start pass runs in persistent mode only");
+    if (band >= 0 && o.mode == SALO_MODE_PLAIN)
+        return fail(SALO_ERR_UNSUPPORTED, "the banded pass runs in persistent mode only");
     if (n_pairs == 0) return SALO_OK;
 
     Workspace *ws = nullptr;
@@ -249,6 +261,7 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     p.packed_ok = scoring_packed_ok(scoring.match, scoring.mismatch) ? 1 : 0;
     p.q_nmask = masks.q;
     p.t_nmask = masks.t;
+    p.band = band;
     // binary16 cells cannot give an N column the mismatch: off with masks
     p.half_ok = !o.no_f16 && !nm && scoring_half_ok(scoring.match, scoring.mismatch,
                                                     scoring.gap_open, scoring.gap_extend);
@@ -292,7 +305,8 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
         return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports lanes 2..64");
     st = ensure_plan(*ws, n_pairs, stream);
     if (st != SALO_OK) return st;
-    const BinTable bt = make_bin_table(cols, o.lanes);
+    const BinTable bt =
+        make_bin_table(cols, o.lanes ? o.lanes : (band >= 0 ? band_lanes(band, cols) : 0));
     p.n_bins = bt.n_bins;
     PlanBuffers pb{ws->keys, ws->order, ws->hist, ws->block_sums, ws->binstat};
     hipError_t e = launch_plan(p, bt, pb, stream);
@@ -358,6 +372,20 @@ salo_status_t salo_align_starts(const uint8_t *q_seqs, const uint32_t *q_nmask,
     const StartArgs sa{score, q_end, t_end};
     return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, nullptr,
                      out_qstart, out_tstart, stream, opts, &sa, NMasks{q_nmask, t_nmask});
+}
+
+salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                      const uint8_t *t_seqs, const int64_t *t_offsets,
+                                      int64_t n_pairs, salo_scoring_t scoring, int32_t band,
+                                      int32_t *out_score, int32_t *out_qend, int32_t *out_tend,
+                                      hipStream_t stream, const salo_options_t *opts) {
+    if (band < 0 || band > SALO_MAX_LEN)
+        return fail(SALO_ERR_INVALID, "band must be in [0, 65535]");
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                out_score, out_qend, out_tend);
+    if (st != SALO_OK) return st;
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
+                     out_qend, out_tend, stream, opts, nullptr, NMasks{nullptr, nullptr}, band);
 }
 
 salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,

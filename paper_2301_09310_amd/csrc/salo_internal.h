@@ -77,6 +77,8 @@ struct KParams {
     // an N scores mismatch against every base); nullptr: no N
     const uint32_t *q_nmask;
     const uint32_t *t_nmask;
+    // banded pass: only cells with |i - j| <= band exist (-1: no band)
+    int32_t band;
     int32_t force_int32;
     int32_t packed_ok;             // scoring admits 16-bit packed cells
     int32_t half_ok;               // scoring admits binary16 cells (and no_f16 is off)
@@ -132,6 +134,22 @@ inline bool scoring_half_ok(int32_t match, int32_t mismatch, int32_t gap_open,
                             int32_t gap_extend) {
     return half_value_ok(match) && half_value_ok(mismatch) &&
            (int64_t)gap_open + gap_extend <= kHalfExact && gap_extend <= kHalfExact;
+}
+
+// Boundary-slot rows of a banded unit with R target rows.  A chunk reads
+// its left neighbour's column only on rows c0-w-1 .. c0-1+w (2w+1 rows), so
+// a ring of 2w+2 rows, rounded up to a power of two, holds them; *wrap is
+// the ring's row mask.  A unit with no more rows than that keeps every row
+// (mask all ones).
+__host__ __device__ inline int band_slot_rows(int R, int w, uint32_t *wrap) {
+    int64_t ring = 1;
+    while (ring < 2 * (int64_t)w + 2) ring <<= 1;
+    if (ring >= R) {
+        *wrap = 0xFFFFFFFFu;
+        return R;
+    }
+    *wrap = (uint32_t)ring - 1u;
+    return (int)ring;
 }
 
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,

@@ -283,7 +283,18 @@ enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
 // pos0: first position (in processing order) of the unit's pairs.
 // [g0, g0 + gn): the groups processed in this pass (all G normally; fewer
 // when the unit's boundary columns do not fit one slot together).
-template <int K, int CT, bool REV, bool NM>
+//
+// BAND (SALoBa, Section VII-B: only cells near the main diagonal): cells
+// with |i - j| > P.band do not exist.  A chunk of columns [c0, c0 + W*K)
+// then only runs rows max(0, c0 - w) .. min(R-1, c0 + W*K - 1 + w); rows
+// above that range are outside the band in every column of the chunk, so
+// the zero column state stands for them exactly.  Every cell outside the
+// band has its H forced to 0 before E, F and the row maximum read it: the
+// band is contiguous in every row and column, so an out-of-band cell left
+// of (below) the band only ever sees the boundary's E (F), and one right
+// of (above) it only feeds other out-of-band cells -- with H = 0 the
+// in-band cells see exactly the boundary values of the restricted table.
+template <int K, int CT, bool REV, bool NM, bool BAND>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                          BaseStream qm, BaseStream tm,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
@@ -292,6 +303,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     constexpr bool PK = CT != kCellWide;
     constexpr int NPG = PK ? 2 : 1;
     static_assert(K % 4 == 0 && K <= 32, "K must be 4..32, multiple of 4");
+    static_assert(!(BAND && (REV || NM)), "the banded pass is forward, without N masks");
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / W;          // W is a power of two
     const int l = lane & (W - 1);
@@ -311,7 +323,16 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     const int R = wave_max(rmax);
     // no target rows: every score is 0 and no boundary row may be touched
     const int Cw = wave_max((mmax + W * K - 1) / (W * K));
-    const int C = R > 0 ? Cw : 0;
+    int C = R > 0 ? Cw : 0;
+    // banded: half-width w; a chunk starting past column R-1+w has no cell
+    // in the band, nor does any chunk after it
+    const int bw = BAND ? P.band : 0;
+    if constexpr (BAND) {
+        if (C > 0) C = min(C, (R - 1 + bw) / (W * K) + 1);
+    }
+    // boundary rows live at slot row (row & rwrap): a ring when banded
+    uint32_t rwrap = 0xFFFFFFFFu;
+    if constexpr (BAND) (void)band_slot_rows(R, bw, &rwrap);
     const int Gs = gn;           // groups sharing the slot, row-interleaved
     // slot column of this lane's group; lanes of groups outside this pass
     // still issue the (unused) boundary prefetch, so they read column 0
@@ -339,31 +360,41 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     const uint32_t NBE2 =
         (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(-beta)) * 0x10001u;
 
-    // per-lane target stream geometry (per pair of the group)
-    int64_t twi[NPG];
-    uint32_t tsh[NPG];
-#pragma unroll
-    for (int h = 0; h < NPG; ++h) {
-        // forward: lane l reads row s - l at base t0 + s - l, 16 rows per
-        // word starting at t0 - l; REV: base t0 - (s - l), so each 16-row
-        // word is the 16 bases ending at t0 + l - s0, reversed, and the
-        // word index steps down
-        const int64_t p0 = REV ? pr[h].t0 + l - 15 : pr[h].t0 - l;
-        twi[h] = p0 >> 4;                    // floor for negatives
-        tsh[h] = (uint32_t)(p0 & 15) * 2u;
-    }
-
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
     const Slot bslot{slot};
-    // slot byte offsets: row r of this lane's group is at r * row_bytes +
-    // ld_lane; the row a lane writes at step s is s - l, hence st_lane
-    // (rows below 64 Ki and at most 64 groups keep every offset in 32 bits)
+    // slot byte offsets: row r of this lane's group is at (r & rwrap) *
+    // row_bytes + ld_lane; a row past the rows the previous chunk wrote
+    // reads as 0 through the descriptor's range check (rows below 64 Ki and
+    // at most 64 groups keep every offset in 32 bits)
     const uint32_t row_bytes = (uint32_t)Gs * 8u;
     const uint32_t ld_lane = (uint32_t)gs * 8u;
-    const int32_t st_lane = (gs - l * Gs) * 8;
 
     for (int c = 0; c < C; ++c) {
         const int col0 = c * W * K + l * K;
+        const int c0 = c * W * K;
+        // rows of this chunk: r0 .. r0 + nrows - 1 (all rows unbanded);
+        // step s runs row r0 + s - l on lane l
+        const int r0 = BAND ? max(0, c0 - bw) : 0;
+        const int nrows = BAND ? min(R - 1, c0 + W * K - 1 + bw) - r0 + 1 : R;
+        // last row the previous chunk wrote to the slot
+        const int bnd_hi = BAND ? min(R - 1, c0 - 1 + bw) : R - 1;
+        auto slot_off = [&](int row) -> uint32_t {
+            return row <= bnd_hi ? ld_lane + ((uint32_t)row & rwrap) * row_bytes
+                                 : (uint32_t)kSlotBytes;
+        };
+        // per-lane target stream geometry (per pair of the group)
+        int64_t twi[NPG];
+        uint32_t tsh[NPG];
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) {
+            // forward: lane l reads row r0 + s - l at base t0 + r0 + s - l,
+            // 16 rows per word starting at t0 + r0 - l; REV: base
+            // t0 - (s - l), so each 16-row word is the 16 bases ending at
+            // t0 + l - s0, reversed, and the word index steps down
+            const int64_t p0 = REV ? pr[h].t0 + l - 15 : pr[h].t0 + r0 - l;
+            twi[h] = p0 >> 4;                    // floor for negatives
+            tsh[h] = (uint32_t)(p0 & 15) * 2u;
+        }
         // query selectors (PK) or query bases (wide) of this lane's K columns
         uint32_t SEL[K];
         {
@@ -451,13 +482,20 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             fifo[r] = make_uint2(0u, 0u);
-            if (have_bnd) {
-                const int rr = min(r, R - 1);
-                fifo[r] = bslot.load(ld_lane + (uint32_t)rr * row_bytes);
+            if (have_bnd) fifo[r] = bslot.load(slot_off(r0 + r));
+        }
+        if constexpr (BAND) {
+            // lane 0's first diagonal: H(r0 - 1, c0 - 1), inside the band
+            if (have_bnd && r0 > 0) {
+                const uint32_t hd0 = bslot.load(slot_off(r0 - 1)).x;
+                hprev = first_lane ? hd0 : 0u;
             }
         }
+        // banded: i - col0 at step 0; the lane's in-band columns at step s
+        // are k in [dl + s - w, dl + s + w]
+        const int dl = r0 - c0 - l * (K + 1);
 
-        const int S = R + W - 1;
+        const int S = nrows + W - 1;
         uint32_t tw_lo[NPG], tw_hi[NPG];
 #pragma unroll
         for (int h = 0; h < NPG; ++h) {
@@ -504,12 +542,20 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             for (int j = 0; j < 4; ++j) {
                 const int s = s0 + j;
                 if (s < S) {
-                const int i = s - l;
+                const int i = r0 + s - l;
                 const uint2 bnd = fifo[j & 3];
-                if (have_bnd) {
-                    const int rr = min(s + 4, R - 1);
-                    fifo[j & 3] = bslot.load(ld_lane + (uint32_t)rr * row_bytes);
+                if (have_bnd) fifo[j & 3] = bslot.load(slot_off(r0 + s + 4));
+                // banded: bit k set when column col0 + k of row i is in the band
+                uint32_t bmask = 0xFFFFFFFFu;
+                if constexpr (BAND) {
+                    const int lo = max(dl + s - bw, 0);
+                    const int hi = min(dl + s + bw + 1, K);
+                    bmask = hi > lo ? (0xFFFFFFFFu >> (32 - (hi - lo))) << lo : 0u;
                 }
+                // all ones, or 0 for a column outside the band
+                auto inband = [&](int k) -> uint32_t {
+                    return BAND ? (uint32_t)((int32_t)(bmask << (31 - k)) >> 31) : 0xFFFFFFFFu;
+                };
                 const uint32_t hin = shift_in(hout, bnd.x, first_lane);
                 const uint32_t ein = shift_in(eout, bnd.y, first_lane);
                 // every lane runs every step: rows outside [0, n) of a pair
@@ -539,7 +585,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const uint32_t f = F[k];
-                        const uint32_t hh = pmax3(H[k], f, e);
+                        const uint32_t hh = pmax3(H[k], f, e) & inband(k);
                         H[k] = hh;
                         const uint32_t ha = hadd(hh, NAL2);
                         F[k] = hmax(hadd(f, NBE2), ha);
@@ -568,7 +614,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const uint32_t f = F[k];
-                        const uint32_t hh = pmax3(H[k], f, e);
+                        const uint32_t hh = pmax3(H[k], f, e) & inband(k);
                         H[k] = hh;
                         const uint32_t ha = psub(hh, AL2);
                         F[k] = pmax(psub(f, BE2), ha);
@@ -589,7 +635,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const int f = (int)F[k];
-                        const int hh = max3i((int)H[k], f, (int)e);
+                        const int hh = max3i((int)H[k], f, (int)e) & (int)inband(k);
                         H[k] = (uint32_t)hh;
                         const int ha = hh - alpha;
                         F[k] = (uint32_t)max3i(f - beta, ha, 0);
@@ -631,10 +677,12 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                 make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
                     }
                 }
-                // the group's last lane holds row s - (W-1): a real row once
-                // s >= W-1 (and always below R, as s < R + W - 1)
+                // the group's last lane holds row r0 + s - (W-1): one of the
+                // chunk's rows once s >= W-1 (and never past them, as
+                // s < nrows + W - 1)
                 if (write_bnd && s >= W - 1 && last_lane)
-                    bslot.store((uint32_t)(st_lane + s * (int32_t)row_bytes), hout, eout);
+                    bslot.store(ld_lane + ((uint32_t)(r0 + s - (W - 1)) & rwrap) * row_bytes,
+                                hout, eout);
                 }  // s < S
             }
         }
@@ -687,7 +735,7 @@ __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, in
     return __builtin_amdgcn_readfirstlane(all16 ? (allh ? kCellF16 : kCellU16) : kCellWide);
 }
 
-template <int K, bool REV, bool NM>
+template <int K, bool REV, bool NM, bool BAND>
 __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                              BaseStream qm, BaseStream tm,
                                              int64_t pos0, int npairs, int W, uint32_t *slot,
@@ -701,10 +749,13 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
         rmax = max(rmax, r.n);
     }
     const int R = wave_max(rmax);
+    // slot rows per group: every target row, or the banded ring
+    uint32_t wrap = 0;
+    const int rows = BAND ? band_slot_rows(R, P.band, &wrap) : R;
     // groups whose boundary columns fit one slot together; a larger unit is
     // processed in several passes of that many groups.  One call site per
     // instantiation keeps run_unit inlined.
-    const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(R, 1)));
+    const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(rows, 1)));
     const int passes = (G + fit - 1) / fit;
     // with N masks the host turns binary16 cells off (their table cannot
     // give an N column the mismatch), so NM never instantiates them
@@ -712,17 +763,17 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     if (!NM && ct == kCellF16) {
         if constexpr (!NM) {
             for (int ps = 0; ps < passes; ++ps)
-                run_unit<K, kCellF16, REV, false>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
+                run_unit<K, kCellF16, REV, false, BAND>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
                                                   ps * fit, min(fit, G - ps * fit), W, slot, lds);
         }
     } else if (ct == kCellU16 || ct == kCellF16) {
         for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, kCellU16, REV, NM>(P, qs, ts, qm, tm, pos0, pos0 + npairs, ps * fit,
+            run_unit<K, kCellU16, REV, NM, BAND>(P, qs, ts, qm, tm, pos0, pos0 + npairs, ps * fit,
                                            min(fit, G - ps * fit), W, slot, lds);
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;
-            run_unit<K, kCellWide, REV, NM>(P, qs, ts, qm, tm, pos0 + (int64_t)half * G,
+            run_unit<K, kCellWide, REV, NM, BAND>(P, qs, ts, qm, tm, pos0 + (int64_t)half * G,
                                             pos0 + npairs, ps * fit, min(fit, G - ps * fit), W,
                                             slot, lds);
         }
@@ -751,7 +802,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pos0 = u * ppu;
         const int np = (int)min<int64_t>(ppu, P.n_pairs - pos0);
-        process_unit<K, false, NM>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved);
+        process_unit<K, false, NM, false>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved);
     }
 }
 
@@ -760,8 +811,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
 // atomic counter until the planned units are exhausted.  The lane-group
 // width comes from the unit's bin; the query columns per lane (K) are fixed
 // per launch so every width shares one register budget.  REV is the start
-// pass (reversed prefixes ending at the forward answers); NM reads N masks.
-template <int K, bool REV, bool NM>
+// pass (reversed prefixes ending at the forward answers); NM reads N masks;
+// BAND restricts the table to a diagonal band.
+template <int K, bool REV, bool NM, bool BAND>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM>, 8))) void persistent_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
     BaseStream qs, ts, qm, tm;
@@ -790,7 +842,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
         const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
         const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
-        process_unit<K, REV, NM>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved);
+        process_unit<K, REV, NM, BAND>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved);
     }
 }
 
@@ -825,14 +877,17 @@ bool persistent_lanes_supported(int lanes) {
            lanes == 64;
 }
 
-template <bool REV, bool NM>
+template <bool REV, bool NM, bool BAND = false>
 hipError_t launch_persistent_t(const KParams &p, int cols, int grid, hipStream_t stream) {
     if (cols == 32)
-        hipLaunchKernelGGL((persistent_kernel<32, REV, NM>), dim3(grid), dim3(kWave), 0, stream, p);
+        hipLaunchKernelGGL((persistent_kernel<32, REV, NM, BAND>), dim3(grid), dim3(kWave), 0,
+                           stream, p);
     else if (cols == 16)
-        hipLaunchKernelGGL((persistent_kernel<16, REV, NM>), dim3(grid), dim3(kWave), 0, stream, p);
+        hipLaunchKernelGGL((persistent_kernel<16, REV, NM, BAND>), dim3(grid), dim3(kWave), 0,
+                           stream, p);
     else if (cols == 8)
-        hipLaunchKernelGGL((persistent_kernel<8, REV, NM>), dim3(grid), dim3(kWave), 0, stream, p);
+        hipLaunchKernelGGL((persistent_kernel<8, REV, NM, BAND>), dim3(grid), dim3(kWave), 0,
+                           stream, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -840,6 +895,10 @@ hipError_t launch_persistent_t(const KParams &p, int cols, int grid, hipStream_t
 
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream) {
     const bool nm = p.q_nmask || p.t_nmask;
+    if (p.band >= 0) {
+        if (nm || p.in_score) return hipErrorInvalidValue;
+        return launch_persistent_t<false, false, true>(p, cols, grid, stream);
+    }
     if (p.in_score)
         return nm ? launch_persistent_t<true, true>(p, cols, grid, stream)
                   : launch_persistent_t<true, false>(p, cols, grid, stream);

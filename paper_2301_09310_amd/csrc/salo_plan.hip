@@ -54,10 +54,15 @@ __device__ __forceinline__ bool pair_packed(const KParams &P, int64_t m, int64_t
 
 // First bin of the pair's kind (16- or 32-bit) whose query range holds m
 // and whose lane-group width keeps the boundary columns of a whole unit in
-// one slot (n rows x 64/W groups x 2 words); else the last bin of the kind.
+// one slot (n rows, or the banded ring, x 64/W groups x 2 words); else the
+// last bin of the kind.
 __device__ __forceinline__ int pair_bin(const KParams &P, const BinTable &bt, int64_t m,
                                         int64_t n) {
     const int want = pair_packed(P, m, n) ? 1 : 0;
+    if (P.band >= 0) {
+        uint32_t wrap = 0;
+        n = band_slot_rows((int)n, P.band, &wrap);
+    }
     int last = 0;
     for (int b = 0; b < bt.n_bins; ++b) {
         if (bt.packed[b] != want) continue;

@@ -336,6 +336,46 @@ def long_uneven(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch:
     return b
 
 
+def anchored_long(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch:
+    """Anchored long extension, the input of banded extension: the long
+    uneven workload's lengths and error model (source length
+    round(exp(U[ln 500, ln 5000])), target length round(source *
+    U[1.1, 1.5]), 5% substitutions, 3% indels of geometric length, mean 2),
+    but with the source at target offset 0, as when both sequences start at
+    the end of a seed: the best path starts near cell (0, 0) and stays near
+    the main diagonal."""
+    q_parts, t_parts = [], []
+    for c0 in range(0, n_pairs, CHUNK_PAIRS):
+        n = min(CHUNK_PAIRS, n_pairs - c0)
+        if progress is not None:
+            progress(c0, n_pairs)
+        rng = np.random.default_rng([seed, 6, c0 // CHUNK_PAIRS])
+        src_lens = np.rint(np.exp(rng.uniform(np.log(500), np.log(5000), n))).astype(np.int64)
+        tl = np.rint(src_lens * rng.uniform(1.1, 1.5, n)).astype(np.int64)
+        left = np.zeros(n, np.int64)
+        right = tl - src_lens
+        src = _rand_bases(rng, src_lens.sum())
+        t, tl = _build_targets(rng, src, src_lens, left, right)
+        mq, ml = _mutate(rng, src, src_lens, 0.05, 0.03, geometric=True)
+        q_parts.append((mq, ml))
+        t_parts.append((t, tl))
+    b = _assemble(q_parts, t_parts)
+    b.name = "anchored_long"
+    return b
+
+
+def band_cells(q_lens, t_lens, band: int) -> np.ndarray:
+    """Per pair, the number of cells (i, j), 0 <= i < t_len, 0 <= j < q_len,
+    with |i - j| <= band: the sum over diagonals d = j - i of their length."""
+    q_lens = np.asarray(q_lens, np.int64)
+    t_lens = np.asarray(t_lens, np.int64)
+    total = np.zeros(q_lens.shape, np.int64)
+    for d in range(-band, band + 1):
+        lo = max(0, -d)
+        total += np.maximum(0, np.minimum(t_lens, q_lens - d) - lo)
+    return total
+
+
 def mixed(seed: int = 0, n_pairs: int = 4_000_000, progress=None) -> Batch:
     """Batched mixed workload: source length drawn from a mixture of
     60% U{100..300}, 35% U{300..1000}, 5% U{1000..10000}; target length
@@ -397,4 +437,5 @@ WORKLOADS = {
     "short_reads": short_reads,
     "long_uneven": long_uneven,
     "mixed": mixed,
+    "anchored_long": anchored_long,
 }

@@ -89,6 +89,9 @@ def load(path: str | None = None):
                                            vp, ctypes.POINTER(Options)]
         lib.salo_align_batch_n.restype = i32
         lib.salo_pack_bases.restype = i32
+        lib.salo_align_batch_banded.argtypes = [vp, vp, vp, vp, i64, Scoring, i32, vp, vp, vp,
+                                                vp, ctypes.POINTER(Options)]
+        lib.salo_align_batch_banded.restype = i32
         if path is None:
             _lib = lib
         return lib
@@ -166,6 +169,40 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
                                     t_seqs.data_ptr(), tm, t_offsets.data_ptr(), n, sc,
                                     out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
                                     _stream_handle(stream), ctypes.byref(opts))
+    _check(lib, st)
+    return out
+
+
+def _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets):
+    import torch
+    n = q_offsets.numel() - 1
+    if t_offsets.numel() - 1 != n:
+        raise ValueError("offset arrays differ in length")
+    for name, t, dt in (("q_seqs", q_seqs, torch.uint8), ("t_seqs", t_seqs, torch.uint8),
+                        ("q_offsets", q_offsets, torch.int64),
+                        ("t_offsets", t_offsets, torch.int64)):
+        if not t.is_cuda or t.dtype != dt or not t.is_contiguous():
+            raise ValueError("%s must be a contiguous %s CUDA tensor" % (name, dt))
+    return n
+
+
+def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4, 6, 1),
+                 out=None, stream=None, **options):
+    """Banded alignment (salo_align_batch_banded): Eq. 1 over the cells with
+    |i - j| <= band.  Arguments and result as align_batch; options as
+    align_batch (mode 'plain' is not supported)."""
+    import torch
+    lib = load()
+    n = _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets)
+    if out is None:
+        dev = q_offsets.device
+        out = tuple(torch.empty(max(n, 0), dtype=torch.int32, device=dev) for _ in range(3))
+    sc = Scoring(*[int(x) for x in scoring])
+    opts = make_options(**options)
+    st = lib.salo_align_batch_banded(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                                     t_offsets.data_ptr(), n, sc, int(band), out[0].data_ptr(),
+                                     out[1].data_ptr(), out[2].data_ptr(),
+                                     _stream_handle(stream), ctypes.byref(opts))
     _check(lib, st)
     return out
 

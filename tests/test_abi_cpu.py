@@ -31,7 +31,7 @@ def test_header_declares_the_boundary():
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
               "salo_error_count", "salo_last_timing", "salo_set_bins", "salo_get_bins",
               "salo_last_error", "salo_release", "salo_version", "salo_pack_bases",
-              "salo_align_starts", "salo_align_batch_n"]:
+              "salo_align_starts", "salo_align_batch_n", "salo_align_batch_banded"]:
         assert n in names
 
 
@@ -169,3 +169,19 @@ def test_masked_align_validation(lib):
     assert "mask" in lib.salo_last_error().decode()
     assert f(ADDR, None, ADDR, ADDR, None, ADDR, -1, SC, ADDR, ADDR, ADDR, NULL,
              ctypes.byref(o)) == -1
+
+
+def test_banded_validation(lib):
+    o = salo.make_options()
+    f = salo.load().salo_align_batch_banded
+    assert f(None, None, None, None, 0, SC, 5, None, None, None, NULL, ctypes.byref(o)) == 0
+    assert f(ADDR, ADDR, ADDR, ADDR, 5, SC, -1, ADDR, ADDR, ADDR, NULL, ctypes.byref(o)) == -1
+    assert "band" in lib.salo_last_error().decode()
+    assert f(ADDR, ADDR, ADDR, ADDR, 5, SC, 65536, ADDR, ADDR, ADDR, NULL,
+             ctypes.byref(o)) == -1
+    assert f(ADDR, ADDR, ADDR, ADDR, -1, SC, 5, ADDR, ADDR, ADDR, NULL, ctypes.byref(o)) == -1
+    assert f(ADDR + 1, ADDR, ADDR, ADDR, 5, SC, 5, ADDR, ADDR, ADDR, NULL,
+             ctypes.byref(o)) == -1
+    p = salo.make_options(mode="plain")
+    assert f(ADDR, ADDR, ADDR, ADDR, 5, SC, 5, ADDR, ADDR, ADDR, NULL, ctypes.byref(p)) == -5
+    assert "persistent" in lib.salo_last_error().decode()

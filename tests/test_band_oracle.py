@@ -144,3 +144,37 @@ def test_planted_mistake_is_caught(name):
     with tempfile.TemporaryDirectory() as tmp:
         assert _check(_mutant(src, tmp, "real"), seed=3, count=25)
         assert not _check(_mutant(src.replace(old, new), tmp, name), seed=3, count=25)
+
+
+def test_threaded_calls_agree():
+    b = I.random_pairs(9, 97, 120, related=0.7)
+    one = O.align_banded(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, 9, threads=1)
+    many = O.align_banded(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, 9, threads=7)
+    for x, y in zip(one, many):
+        assert np.array_equal(x, y)
+
+
+def test_band_cell_count():
+    rng = np.random.default_rng(4)
+    ql = rng.integers(0, 40, 60)
+    tl = rng.integers(0, 40, 60)
+    for w in (0, 1, 5, 50):
+        got = I.band_cells(ql, tl, w)
+        for p in range(60):
+            want = sum(1 for i in range(tl[p]) for j in range(ql[p]) if abs(i - j) <= w)
+            assert got[p] == want
+
+
+def test_anchored_workload_shape():
+    b = I.anchored_long(0, 2000)
+    ql, tl = b.q_lens(), b.t_lens()
+    assert b.n_pairs == 2000
+    assert ql.min() >= 250 and ql.max() <= 8000
+    # the source starts the target: the best path starts at or near (0, 0)
+    sub = b.subset(np.arange(20))
+    s, qe, te = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets)
+    qs, ts = O.start_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, s, qe, te)
+    assert np.all(qs <= 64) and np.all(ts <= 64)
+    # and a band of 100 keeps the whole best alignment for nearly every pair
+    bs, _, _ = O.align_banded(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, 100)
+    assert np.mean(bs == s) >= 0.9
