@@ -197,8 +197,11 @@ salo_status_t salo_align_starts(const uint8_t *q_seqs, const uint32_t *q_nmask,
  * band: 0..65535 (else SALO_ERR_INVALID).  Other arguments, options and
  * errors as salo_align_batch_ex; runs the persistent mode
  * (opts->mode = SALO_MODE_PLAIN returns SALO_ERR_UNSUPPORTED).  With
- * opts->lanes = 0 the lane-group width is chosen from the band: the
- * largest power of two W with W * cols <= band / 2 (at least 1).
+ * opts->cols = 0 the query columns per lane are 8 for a band of at most
+ * 160, else 16.  With opts->lanes = 0 the lane-group width W is chosen from the band and the
+ * batch: the largest power of two with W * cols <= max(64, band / 2), raised
+ * (up to 64) until the batch fills about two units of work per resident
+ * wave (a unit holds 128 / W pairs).
  */
 salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_offsets,
                                       const uint8_t *t_seqs, const int64_t *t_offsets,

@@ -200,13 +200,18 @@ struct NMasks {
     const uint32_t *q, *t;   // either may be nullptr
 };
 
-// Lanes per pair group of the banded pass: chunks of about w/2 columns.
-// A chunk of W*K columns runs W*K + 2w rows (plus the W-1 step ramp) to
-// cover its (2w+1)-wide stripe of the band, so narrow chunks waste fewer
-// cells; the boundary column written per chunk bounds how narrow they go.
-int band_lanes(int32_t band, int cols) {
+// Lanes per pair group of the banded pass.  A chunk of W*K columns runs
+// W*K + 2w rows (plus the W-1 step ramp) to cover its (2w+1)-wide stripe of
+// the band, so narrow chunks compute fewer cells outside it; but a unit
+// holds 128/W pairs, and a batch with too few units per resident wave ends
+// on a long tail.  Measured on MI355X (200,000 anchored pairs of 500-5,000
+// bases, bands 32..300): chunks of max(64, w/2) columns rounded down to a
+// power of two, and at least about two units per wave.
+int band_lanes(int32_t band, int cols, int64_t n_pairs, int64_t grid) {
+    const int64_t target = band / 2 > 64 ? band / 2 : 64;
     int w = 1;
-    while (w < 64 && (int64_t)2 * w * 2 * cols <= band) w <<= 1;
+    while (w < 64 && (int64_t)2 * w * cols <= target) w <<= 1;
+    while (w < 64 && n_pairs * w < 2 * 128 * grid) w <<= 1;
     return w;
 }
 
@@ -238,7 +243,10 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     // 8 or 16 query columns per lane, 2 per SIMD for 32
     // (kernels that read N masks are compiled for 2 per SIMD)
     const bool nm = masks.q != nullptr || masks.t != nullptr;
-    const int cols_req = o.cols ? o.cols : 16;
+    // query columns per lane: 16, or 8 for a banded pass with a band of at
+    // most 160 (measured: the narrower chunks it allows waste fewer cells)
+    const int cols_default = (band >= 0 && band <= 160) ? 8 : 16;
+    const int cols_req = o.cols ? o.cols : cols_default;
     const int wpc = o.waves_per_cu ? o.waves_per_cu : (cols_req >= 32 || nm ? 8 : 12);
     const int64_t grid = (int64_t)ws->cus * wpc;
     st = ensure_slots(*ws, grid, stream);
@@ -298,7 +306,7 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     }
 
     // persistent, length-binned
-    const int cols = o.cols ? o.cols : 16;
+    const int cols = cols_req;
     if (cols != 8 && cols != 16 && cols != 32)
         return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports cols 8, 16 or 32");
     if (o.lanes && !persistent_lanes_supported(o.lanes))
@@ -306,7 +314,8 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     st = ensure_plan(*ws, n_pairs, stream);
     if (st != SALO_OK) return st;
     const BinTable bt =
-        make_bin_table(cols, o.lanes ? o.lanes : (band >= 0 ? band_lanes(band, cols) : 0));
+        make_bin_table(cols, o.lanes ? o.lanes
+                                     : (band >= 0 ? band_lanes(band, cols, n_pairs, grid) : 0));
     p.n_bins = bt.n_bins;
     PlanBuffers pb{ws->keys, ws->order, ws->hist, ws->block_sums, ws->binstat};
     hipError_t e = launch_plan(p, bt, pb, stream);

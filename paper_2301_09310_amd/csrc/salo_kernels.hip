@@ -494,6 +494,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         // banded: i - col0 at step 0; the lane's in-band columns at step s
         // are k in [dl + s - w, dl + s + w]
         const int dl = r0 - c0 - l * (K + 1);
+        // lane l covers all its columns at step s when dl + s - w <= 0 and
+        // dl + s + w >= K - 1: for every lane exactly when s_lo <= s <= s_hi
+        const int s_hi = bw - (r0 - c0);
+        const int s_lo = K - 1 + (W - 1) * (K + 1) - bw - (r0 - c0);
 
         const int S = nrows + W - 1;
         uint32_t tw_lo[NPG], tw_hi[NPG];
@@ -520,7 +524,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             tn_nx[h] = 0u;
             if constexpr (NM) tn_nx[h] = target_n_bits(h, 0);
         }
-        for (int s0 = 0; s0 < S; s0 += 4) {
+        // steps s0 .. s0+3 for s0 = sa, sa+4, ... < sb (sa a multiple of 4)
+        auto run_steps = [&](int sa, int sb, auto masked) {
+        for (int s0 = sa; s0 < sb; s0 += 4) {
             if ((s0 & 15) == 0) {
                 // the next 16 target bases of each pair, already in flight;
                 // start loading the 16 after them
@@ -538,6 +544,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 }
             }
             const uint32_t jsh = (uint32_t)(s0 & 15) * 2u;
+            // four steps; `masked` (compile time) applies the band mask
+            auto steps4 = [&](auto masked) {
+            constexpr bool MASK = BAND && decltype(masked)::value;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int s = s0 + j;
@@ -547,14 +556,14 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 if (have_bnd) fifo[j & 3] = bslot.load(slot_off(r0 + s + 4));
                 // banded: bit k set when column col0 + k of row i is in the band
                 uint32_t bmask = 0xFFFFFFFFu;
-                if constexpr (BAND) {
+                if constexpr (MASK) {
                     const int lo = max(dl + s - bw, 0);
                     const int hi = min(dl + s + bw + 1, K);
                     bmask = hi > lo ? (0xFFFFFFFFu >> (32 - (hi - lo))) << lo : 0u;
                 }
                 // all ones, or 0 for a column outside the band
                 auto inband = [&](int k) -> uint32_t {
-                    return BAND ? (uint32_t)((int32_t)(bmask << (31 - k)) >> 31) : 0xFFFFFFFFu;
+                    return MASK ? (uint32_t)((int32_t)(bmask << (31 - k)) >> 31) : 0xFFFFFFFFu;
                 };
                 const uint32_t hin = shift_in(hout, bnd.x, first_lane);
                 const uint32_t ein = shift_in(eout, bnd.y, first_lane);
@@ -685,6 +694,21 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                 hout, eout);
                 }  // s < S
             }
+            };
+            steps4(masked);
+        }
+        };
+        if constexpr (BAND) {
+            // steps s_lo .. s_hi have every lane's K columns inside the band
+            // (the same for every group of the wave): the 4-step blocks
+            // inside that range skip the mask
+            const int a = min(max(0, (s_lo + 3) & ~3), (S + 3) & ~3);
+            const int b = max(a, min(((s_hi + 1) & ~3), (S + 3) & ~3));
+            run_steps(0, a, std::true_type{});
+            run_steps(a, b, std::false_type{});
+            run_steps(b, S, std::true_type{});
+        } else {
+            run_steps(0, S, std::false_type{});
         }
 
         // resolve this chunk's candidate column per pair
