@@ -11,7 +11,8 @@ recurrence, returning per pair the highest cell score and its end position
 the header of the C file for every reading of the paper it takes), and the
 companion files: ``pack_oracle.c`` (2-bit packing and reverse complement),
 ``start_oracle.c`` (start positions of the best alignment) and
-``band_oracle.c`` (Eq. 1 restricted to a diagonal band, Section VII-B).
+``band_oracle.c`` (Eq. 1 restricted to a diagonal band, Section VII-B) and
+``trace_oracle.c`` (the optimal path between start and end, as a CIGAR).
 
 The shared library is compiled from the C source with gcc on first use
 (and by the repository's build step); it has no dependency on the GPU code.
@@ -28,7 +29,7 @@ import numpy as np
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "gotoh_oracle.c")
 _SRCS = [_SRC, os.path.join(_HERE, "pack_oracle.c"), os.path.join(_HERE, "start_oracle.c"),
-         os.path.join(_HERE, "band_oracle.c")]
+         os.path.join(_HERE, "band_oracle.c"), os.path.join(_HERE, "trace_oracle.c")]
 _LIB = os.path.join(_HERE, "liboracle_gotoh.so")
 _lock = threading.Lock()
 _lib = None
@@ -74,6 +75,9 @@ def _load():
             lib.oracle_align_banded.argtypes = [p, p, p, p, i64, i64, i64, i64, i64, i64,
                                                 p, p, p]
             lib.oracle_align_banded.restype = ctypes.c_int
+            lib.oracle_trace_batch.argtypes = [p, p, p, p, i64, i64, i64, i64, i64,
+                                               p, p, p, p, p, p, p, p]
+            lib.oracle_trace_batch.restype = i64
             lib.oracle_start_batch.argtypes = [p, p, p, p, i64, i64, i64, i64, i64,
                                                p, p, p, p, p]
             lib.oracle_start_batch.restype = i64
@@ -271,3 +275,54 @@ def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4
     if any(rc != 0 for rc in rcs):
         raise MemoryError("oracle_align_banded failed")
     return tuple(out)
+
+
+CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D"}
+
+
+def cigar_capacity(q_offsets, t_offsets) -> np.ndarray:
+    """Offsets of a CIGAR buffer with room for m + n runs per pair (a path
+    between start and end has at most m' + n' - 1 runs)."""
+    cap = np.diff(np.asarray(q_offsets, np.int64)) + np.diff(np.asarray(t_offsets, np.int64))
+    off = np.zeros(len(cap) + 1, np.int64)
+    np.cumsum(cap, out=off[1:])
+    return off
+
+
+def trace_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_start, q_end, t_start, t_end,
+                scoring=(1, -4, 6, 1), cig_off=None):
+    """Oracle of the trace (see the header of trace_oracle.c): per pair the
+    optimal alignment from (q_start, t_start) to (q_end, t_end) as BAM-coded
+    CIGAR runs.  Returns (cig_off, cig, cig_len); cig_len is 0 for score 0
+    and -1 for an inconsistent pair (raises RuntimeError if any)."""
+    lib = _load()
+    n = len(q_offsets) - 1
+    if cig_off is None:
+        cig_off = cigar_capacity(q_offsets, t_offsets)
+    cig_off = np.ascontiguousarray(cig_off, dtype=np.int64)
+    cig = np.zeros(max(int(cig_off[-1]) if n > 0 else 0, 1), np.uint32)
+    cig_len = np.zeros(max(n, 0), np.int64)
+    if n <= 0:
+        return cig_off, cig, cig_len
+    arr = [np.ascontiguousarray(x, dtype=np.int64) for x in (score, q_start, q_end, t_start, t_end)]
+    q_seqs = np.ascontiguousarray(q_seqs, dtype=np.uint8)
+    t_seqs = np.ascontiguousarray(t_seqs, dtype=np.uint8)
+    qb = q_seqs if len(q_seqs) else np.zeros(1, np.uint8)
+    tb = t_seqs if len(t_seqs) else np.zeros(1, np.uint8)
+    q_offsets = np.ascontiguousarray(q_offsets, dtype=np.int64)
+    t_offsets = np.ascontiguousarray(t_offsets, dtype=np.int64)
+    a, b, o, e = (int(x) for x in scoring)
+    bad = lib.oracle_trace_batch(_ptr(qb), _ptr(q_offsets), _ptr(tb), _ptr(t_offsets), n,
+                                 a, b, o, e, *(_ptr(x) for x in arr), _ptr(cig_off), _ptr(cig),
+                                 _ptr(cig_len))
+    if bad < 0:
+        raise MemoryError("oracle_trace_batch failed")
+    if bad > 0:
+        raise RuntimeError("trace oracle: %d inconsistent pairs" % bad)
+    return cig_off, cig, cig_len
+
+
+def cigar_string(cig, start, length) -> str:
+    """Text form of the runs cig[start : start + length]."""
+    return "".join("%d%s" % (int(c) >> 4, CIGAR_OPS[int(c) & 15])
+                   for c in cig[start:start + length])
