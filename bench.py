@@ -141,6 +141,9 @@ def main(argv=None) -> int:
                     help="also time the start-position pass on the timed step's answers")
     ap.add_argument("--band", type=int, default=-1, metavar="W",
                     help="time the banded pass (cells with |i - j| <= W) instead")
+    ap.add_argument("--trace", action="store_true",
+                    help="time the trace pass (CIGAR of each best alignment) instead")
+    ap.add_argument("--trace-workspace-gb", type=float, default=4.0)
     ap.add_argument("--pack", action="store_true",
                     help="time the on-device packing of the workload's reads written as "
                          "characters (forward and reverse-complement)")
@@ -180,6 +183,8 @@ def main(argv=None) -> int:
         return pack_bench(args)
     if args.band >= 0:
         return band_bench(args)
+    if args.trace:
+        return trace_bench(args)
 
     gen = I.WORKLOADS[args.workload]
     t0 = time.time()
@@ -520,6 +525,122 @@ def band_bench(args) -> int:
                        "unbanded_gcups_table_cells": round(rect / (fms * 1e-3) / 1e9, 2),
                        "speedup_vs_unbanded": round(fms / ms, 3),
                        "pairs_with_unbanded_answer": round(same, 4)},
+    }
+    print(json.dumps(rec), flush=True)
+    return 0 if parity_ok else 1
+
+
+def trace_bench(args) -> int:
+    """Time of salo_align_trace on the workload's own answers and starts
+    (computed first, untimed), GCUPS over the cells of the spans it refills
+    (sum of (q_end - q_start + 1) x (t_end - t_start + 1)), parity of sampled
+    CIGARs against the trace oracle, and the oracle timed on the host."""
+    import torch
+    from oracle import oracle as O
+    from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import salo
+    dev = torch.device("cuda:0")
+    gen = I.WORKLOADS[args.workload]
+    t0 = time.time()
+    batch = gen(0, args.pairs) if args.pairs else gen(0)
+    n = batch.n_pairs
+    log("workload %s: %d pairs, generated in %.1fs" % (args.workload, n, time.time() - t0))
+    q, qo, t, to = salo.to_device(batch, dev)
+    stream = torch.cuda.current_stream()
+    ans = salo.align_batch(q, qo, t, to, SCORING, stream=stream)
+    st = salo.align_starts(q, qo, t, to, ans, SCORING, stream=stream)
+    a_np = [x.cpu().numpy().astype(np.int64) for x in ans]
+    s_np = [x.cpu().numpy().astype(np.int64) for x in st]
+    pos = a_np[0] > 0
+    span = int(((a_np[1] - s_np[0] + 1) * (a_np[2] - s_np[1] + 1) * pos).sum())
+    ws = torch.empty(int(args.trace_workspace_gb * (1 << 30)), dtype=torch.uint8, device=dev)
+    cig_off = salo.cigar_offsets(qo, to)
+    opts = dict(lanes=args.lanes, cols=args.cols, waves_per_cu=args.waves_per_cu)
+    out = None
+    for _ in range(max(args.warmup, 1)):
+        out = salo.align_trace(q, qo, t, to, ans, st, SCORING, cig_off=cig_off, workspace=ws,
+                               stream=stream, **opts)
+    torch.cuda.synchronize()
+    log("trace warm-up done; span cells %.3e" % span)
+    ev0 = torch.cuda.Event(enable_timing=True)
+    ev1 = torch.cuda.Event(enable_timing=True)
+    plan_ms, dp_ms = [], []
+    ev0.record(stream)
+    for _ in range(args.steps):
+        out = salo.align_trace(q, qo, t, to, ans, st, SCORING, cig_off=cig_off, workspace=ws,
+                               stream=stream, timing=True, **opts)
+        a, b = salo.last_timing(stream)
+        plan_ms.append(a)
+        dp_ms.append(b)
+    ev1.record(stream)
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / args.steps
+    errors = salo.error_count(stream)
+    gcups = span / (ms * 1e-3) / 1e9
+    log("trace: %.3f ms per step (kernel %s), %.1f GCUPS over span cells, %d errors"
+        % (ms, " ".join("%.2f" % x for x in dp_ms), gcups, errors))
+    off = out[0].cpu().numpy()
+    cig = out[1].cpu().numpy().view(np.uint32)
+    ln = out[2].cpu().numpy().astype(np.int64)
+    runs = int(ln[ln > 0].sum())
+
+    rng = np.random.default_rng(1)
+    k = min(args.parity_sample, n, 2000)
+    idx = np.sort(rng.choice(n, size=k, replace=False))
+    sub = batch.subset(idx)
+    w_ans = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING)
+    w_st = O.start_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, *w_ans,
+                         scoring=SCORING)
+    woff, wcig, wln = O.trace_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets,
+                                    w_ans[0], w_st[0], w_ans[1], w_st[1], w_ans[2], SCORING,
+                                    threads=O.default_threads())
+    parity_ok = errors == 0 and np.array_equal(ln[idx], wln) and all(
+        np.array_equal(cig[off[p]:off[p] + ln[p]], wcig[woff[j]:woff[j] + wln[j]])
+        for j, p in enumerate(idx))
+    log("parity on %d sampled pairs: %s" % (k, "bit-exact" if parity_ok else "MISMATCH"))
+
+    kern_ms = float(np.mean(dp_ms))
+    achieved = OPS_PER_CELL * span / (kern_ms * 1e-3) / 1e12
+    peak = PEAK_TOPS["i32"]
+    roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
+            "unit": "TOP/s", "frac": round(achieved / peak, 4),
+            "traffic": measured_traffic("trace_" + args.workload),
+            "kernel": "persistent_kernel (trace)", "kernel_ms": round(kern_ms, 4),
+            "ops_per_cell": OPS_PER_CELL, "cells": "of the start-to-end spans",
+            "traffic_unit": "bytes per launch", "kernel_source": kernel_source_hash()}
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        m = min(args.cpu_sample, n)
+        csub = batch.subset(np.arange(m))
+        c_ans = O.align_batch(csub.q_seqs, csub.q_offsets, csub.t_seqs, csub.t_offsets, SCORING)
+        c_st = O.start_batch(csub.q_seqs, csub.q_offsets, csub.t_seqs, csub.t_offsets, *c_ans,
+                             scoring=SCORING)
+        thr = O.default_threads()
+        c0 = time.perf_counter()
+        O.trace_batch(csub.q_seqs, csub.q_offsets, csub.t_seqs, csub.t_offsets, c_ans[0],
+                      c_st[0], c_ans[1], c_st[1], c_ans[2], SCORING, threads=thr)
+        dt = time.perf_counter() - c0
+        cspan = int(((c_ans[1] - c_st[0] + 1) * (c_ans[2] - c_st[1] + 1) * (c_ans[0] > 0)).sum())
+        cpu = {"value": round(cspan / dt / 1e9, 4), "unit": "GCUPS over span cells",
+               "cores": thr, "kind": "oracle",
+               "sample": "first %d pairs of the %s batch (%.3e span cells), %.1fs" % (
+                   m, args.workload, cspan, dt)}
+        log("cpu trace oracle: %.3f GCUPS on %d threads" % (cpu["value"], thr))
+
+    rec = {
+        "metric": "GCUPS over the start-to-end spans (bit-exact CIGAR vs oracle), trace pass",
+        "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
+        "warmup": max(args.warmup, 1), "ms_per_step": round(ms, 4), "higher_is_better": True,
+        "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "config": {"workload": args.workload, "pairs": n, "span_cells": span,
+                   "cigar_runs": runs, "scoring": list(SCORING), "lanes": args.lanes,
+                   "cols": args.cols, "workspace_gb": args.trace_workspace_gb,
+                   "dp_ms": round(kern_ms, 4), "plan_ms": round(float(np.mean(plan_ms)), 4),
+                   "parity": "bit-exact on %d sampled pairs" % k
+                   if parity_ok else "MISMATCH on sampled pairs"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
     }
     print(json.dumps(rec), flush=True)
     return 0 if parity_ok else 1

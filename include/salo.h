@@ -210,6 +210,47 @@ salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_of
                                       int32_t *out_tend, hipStream_t stream,
                                       const salo_options_t *opts);
 
+/*
+ * Trace of the best alignment (Section II-A: the path that reaches the
+ * highest cell), as a run-length CIGAR, for the answers of an align call
+ * and a start call on the same inputs and scoring.  For every pair with
+ * score > 0, one optimal alignment from (q_start, t_start) to
+ * (q_end, t_end); when several are optimal, the one chosen walking back from
+ * the end by preferring, at every step, an aligned pair over an I over a D,
+ * and inside a gap, the gap opening at this base over it extending.
+ * Runs are written in alignment order to cigar[cigar_offsets[p] ..] as
+ * uint32 (length << 4) | op with BAM codes: 7 '=' (equal bases), 8 'X'
+ * (unequal bases), 1 'I' (query base against a gap in the target), 2 'D'
+ * (target base against a gap in the query).
+ * Arguments: the align call's sequences, offsets, n_pairs and scoring; the
+ * answers score, q_start, q_end, t_start, t_end (DEVICE int32 [n_pairs],
+ * 4-byte aligned); cigar_offsets (DEVICE int64 [n_pairs + 1], 8-byte
+ * aligned; pair p owns cigar[cigar_offsets[p] .. cigar_offsets[p+1]), and
+ * q_end - q_start + t_end - t_start + 1 runs always suffice); cigar (DEVICE
+ * uint32); cigar_len (DEVICE int32 [n_pairs], fully overwritten: the run
+ * count, 0 for score 0, -1 for a pair whose answers are not Eq. 1's or
+ * whose runs do not fit, -2 for a pair too large for its share of the
+ * workspace; -1 and -2 are counted, see salo_error_count).
+ * workspace: DEVICE scratch of workspace_bytes, 256-byte aligned, owned by
+ * the caller and only used during the call.  Each resident wave (CUs x 12
+ * with 8 columns per lane, CUs x 8 with 16) gets an equal share; a wave
+ * aligns up to 64 / W spans at once (W lanes per span, 4..64 by span
+ * length) and each needs ceil(span length / (W x cols)) x W x cols x
+ * (span rows) / 2 bytes of it.  Too small for 4 KiB per wave:
+ * SALO_ERR_INVALID.
+ * Runs in the persistent mode with 32-bit cells (opts->mode =
+ * SALO_MODE_PLAIN or opts->cols = 32 return SALO_ERR_UNSUPPORTED);
+ * other options and errors as salo_align_batch_ex.
+ */
+salo_status_t salo_align_trace(const uint8_t *q_seqs, const int64_t *q_offsets,
+                               const uint8_t *t_seqs, const int64_t *t_offsets, int64_t n_pairs,
+                               salo_scoring_t scoring, const int32_t *score,
+                               const int32_t *q_start, const int32_t *q_end,
+                               const int32_t *t_start, const int32_t *t_end,
+                               const int64_t *cigar_offsets, uint32_t *cigar,
+                               int32_t *cigar_len, void *workspace, int64_t workspace_bytes,
+                               hipStream_t stream, const salo_options_t *opts);
+
 /* Pre-size the workspace of (current device, stream) for batches of up to
  * max_pairs pairs, so later calls allocate nothing (needed before graph
  * capture).  Synchronous with respect to the host. */

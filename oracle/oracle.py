@@ -290,7 +290,7 @@ def cigar_capacity(q_offsets, t_offsets) -> np.ndarray:
 
 
 def trace_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_start, q_end, t_start, t_end,
-                scoring=(1, -4, 6, 1), cig_off=None):
+                scoring=(1, -4, 6, 1), cig_off=None, threads: int | None = None):
     """Oracle of the trace (see the header of trace_oracle.c): per pair the
     optimal alignment from (q_start, t_start) to (q_end, t_end) as BAM-coded
     CIGAR runs.  Returns (cig_off, cig, cig_len); cig_len is 0 for score 0
@@ -312,11 +312,28 @@ def trace_batch(q_seqs, q_offsets, t_seqs, t_offsets, score, q_start, q_end, t_s
     q_offsets = np.ascontiguousarray(q_offsets, dtype=np.int64)
     t_offsets = np.ascontiguousarray(t_offsets, dtype=np.int64)
     a, b, o, e = (int(x) for x in scoring)
-    bad = lib.oracle_trace_batch(_ptr(qb), _ptr(q_offsets), _ptr(tb), _ptr(t_offsets), n,
-                                 a, b, o, e, *(_ptr(x) for x in arr), _ptr(cig_off), _ptr(cig),
-                                 _ptr(cig_len))
-    if bad < 0:
+    # independent pairs: contiguous ranges on worker threads (cig_off holds
+    # absolute positions, so every range writes into the same cig)
+    workers = max(1, min(threads or 1, n))
+    cuts = np.linspace(0, n, workers + 1).astype(np.int64)
+
+    def run(k):
+        lo, hi = int(cuts[k]), int(cuts[k + 1])
+        if hi <= lo:
+            return 0
+        return lib.oracle_trace_batch(_ptr(qb), _ptr(q_offsets) + 8 * lo, _ptr(tb),
+                                      _ptr(t_offsets) + 8 * lo, hi - lo, a, b, o, e,
+                                      *(_ptr(x) + 8 * lo for x in arr),
+                                      _ptr(cig_off) + 8 * lo, _ptr(cig), _ptr(cig_len) + 8 * lo)
+    if workers == 1:
+        rcs = [run(0)]
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        with ThreadPoolExecutor(workers) as ex:
+            rcs = list(ex.map(run, range(workers)))
+    if any(rc < 0 for rc in rcs):
         raise MemoryError("oracle_trace_batch failed")
+    bad = sum(rcs)
     if bad > 0:
         raise RuntimeError("trace oracle: %d inconsistent pairs" % bad)
     return cig_off, cig, cig_len

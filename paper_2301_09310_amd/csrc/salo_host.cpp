@@ -199,6 +199,42 @@ struct StartArgs {
 struct NMasks {
     const uint32_t *q, *t;   // either may be nullptr
 };
+// Trace pass: the answers' starts, the CIGAR buffers and the code workspace.
+struct TraceArgs {
+    const int32_t *qstart, *tstart;
+    const int64_t *cig_off;
+    uint32_t *cig;
+    int32_t *cig_len;
+    uint8_t *ws;
+    int64_t ws_bytes;
+};
+
+// Bins of the trace pass (32-bit cells, 8 columns per lane by default):
+// lane-group width by span length so that a chunk of W x 8 columns covers
+// short spans without padding and long spans run on whole waves.
+BinTable trace_bin_table(int cols, int forced_lanes) {
+    BinTable bt;
+    std::memset(&bt, 0, sizeof bt);
+    const int32_t hi[] = {4 * cols, 8 * cols, 16 * cols, 32 * cols, 65535};
+    const int32_t lanes[] = {4, 8, 16, 32, 64};
+    int32_t prev = 0;
+    for (int b = 0; b < 5; ++b) {
+        bt.m_lo[b] = prev;
+        bt.m_hi[b] = hi[b];
+        prev = hi[b];
+        bt.packed[b] = 0;
+        bt.lanes[b] = forced_lanes ? forced_lanes : lanes[b];
+        bt.cols[b] = cols;
+    }
+    // the plan expects a bin of each kind; no trace pair is 16-bit
+    bt.m_lo[5] = 0;
+    bt.m_hi[5] = 65535;
+    bt.packed[5] = 1;
+    bt.lanes[5] = 64;
+    bt.cols[5] = cols;
+    bt.n_bins = 6;
+    return bt;
+}
 
 // Lanes per pair group of the banded pass.  A chunk of W*K columns runs
 // W*K + 2w rows (plus the W-1 step ramp) to cover its (2w+1)-wide stripe of
@@ -219,7 +255,8 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
                         const uint8_t *t_seqs, const int64_t *t_offsets, int64_t n_pairs,
                         salo_scoring_t scoring, int32_t *out_score, int32_t *out_qend,
                         int32_t *out_tend, hipStream_t stream, const salo_options_t *opts,
-                        const StartArgs *starts, NMasks masks, int32_t band = -1) {
+                        const StartArgs *starts, NMasks masks, int32_t band = -1,
+                        const TraceArgs *trace = nullptr) {
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
@@ -233,6 +270,10 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
         return fail(SALO_ERR_UNSUPPORTED, "the start pass runs in persistent mode only");
     if (band >= 0 && o.mode == SALO_MODE_PLAIN)
         return fail(SALO_ERR_UNSUPPORTED, "the banded pass runs in persistent mode only");
+    if (trace && o.mode == SALO_MODE_PLAIN)
+        return fail(SALO_ERR_UNSUPPORTED, "the trace pass runs in persistent mode only");
+    if (trace && o.cols != 0 && o.cols != 8 && o.cols != 16)
+        return fail(SALO_ERR_UNSUPPORTED, "the trace pass supports cols 8 or 16");
     if (n_pairs == 0) return SALO_OK;
 
     Workspace *ws = nullptr;
@@ -245,9 +286,11 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     const bool nm = masks.q != nullptr || masks.t != nullptr;
     // query columns per lane: 16, or 8 for a banded pass with a band of at
     // most 160 (measured: the narrower chunks it allows waste fewer cells)
-    const int cols_default = (band >= 0 && band <= 160) ? 8 : 16;
+    // (the trace pass: 8 columns by default, 2 waves per SIMD at 16)
+    const int cols_default = ((band >= 0 && band <= 160) || trace) ? 8 : 16;
     const int cols_req = o.cols ? o.cols : cols_default;
-    const int wpc = o.waves_per_cu ? o.waves_per_cu : (cols_req >= 32 || nm ? 8 : 12);
+    const int wpc = o.waves_per_cu ? o.waves_per_cu
+                                   : (cols_req >= 32 || nm || (trace && cols_req > 8) ? 8 : 12);
     const int64_t grid = (int64_t)ws->cus * wpc;
     st = ensure_slots(*ws, grid, stream);
     if (st != SALO_OK) return st;
@@ -270,6 +313,21 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     p.q_nmask = masks.q;
     p.t_nmask = masks.t;
     p.band = band;
+    if (trace) {
+        const int64_t slot = (trace->ws_bytes / grid) & ~(int64_t)255;
+        if (slot < 4096)
+            return fail(SALO_ERR_INVALID, "trace workspace below 4 KiB per resident wave (" +
+                                              std::to_string(grid) + " waves)");
+        p.in_qstart = trace->qstart;
+        p.in_tstart = trace->tstart;
+        p.trace_ws = trace->ws;
+        p.trace_slot = slot;
+        p.cig_off = trace->cig_off;
+        p.cig = trace->cig;
+        p.cig_len = trace->cig_len;
+        p.force_int32 = 1;
+        p.half_ok = 0;
+    }
     // binary16 cells cannot give an N column the mismatch: off with masks
     p.half_ok = !o.no_f16 && !nm && scoring_half_ok(scoring.match, scoring.mismatch,
                                                     scoring.gap_open, scoring.gap_extend);
@@ -314,8 +372,10 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     st = ensure_plan(*ws, n_pairs, stream);
     if (st != SALO_OK) return st;
     const BinTable bt =
-        make_bin_table(cols, o.lanes ? o.lanes
-                                     : (band >= 0 ? band_lanes(band, cols, n_pairs, grid) : 0));
+        trace ? trace_bin_table(cols, o.lanes)
+              : make_bin_table(cols, o.lanes ? o.lanes
+                                             : (band >= 0 ? band_lanes(band, cols, n_pairs, grid)
+                                                          : 0));
     p.n_bins = bt.n_bins;
     PlanBuffers pb{ws->keys, ws->order, ws->hist, ws->block_sums, ws->binstat};
     hipError_t e = launch_plan(p, bt, pb, stream);
@@ -395,6 +455,37 @@ salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_of
     if (st != SALO_OK) return st;
     return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
                      out_qend, out_tend, stream, opts, nullptr, NMasks{nullptr, nullptr}, band);
+}
+
+salo_status_t salo_align_trace(const uint8_t *q_seqs, const int64_t *q_offsets,
+                               const uint8_t *t_seqs, const int64_t *t_offsets, int64_t n_pairs,
+                               salo_scoring_t scoring, const int32_t *score,
+                               const int32_t *q_start, const int32_t *q_end,
+                               const int32_t *t_start, const int32_t *t_end,
+                               const int64_t *cigar_offsets, uint32_t *cigar,
+                               int32_t *cigar_len, void *workspace, int64_t workspace_bytes,
+                               hipStream_t stream, const salo_options_t *opts) {
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                cigar_len, cigar_len, cigar_len);
+    if (st != SALO_OK) return st;
+    if (n_pairs == 0) return SALO_OK;
+    if (!score || !q_start || !q_end || !t_start || !t_end || !cigar_offsets || !cigar ||
+        !workspace)
+        return fail(SALO_ERR_INVALID, "NULL pointer argument");
+    if ((reinterpret_cast<uintptr_t>(score) | reinterpret_cast<uintptr_t>(q_start) |
+         reinterpret_cast<uintptr_t>(q_end) | reinterpret_cast<uintptr_t>(t_start) |
+         reinterpret_cast<uintptr_t>(t_end) | reinterpret_cast<uintptr_t>(cigar)) & 3)
+        return fail(SALO_ERR_INVALID, "answers and cigar must be 4-byte aligned");
+    if (reinterpret_cast<uintptr_t>(cigar_offsets) & 7)
+        return fail(SALO_ERR_INVALID, "cigar_offsets must be 8-byte aligned");
+    if (reinterpret_cast<uintptr_t>(workspace) & 255)
+        return fail(SALO_ERR_INVALID, "workspace must be 256-byte aligned");
+    if (workspace_bytes <= 0) return fail(SALO_ERR_INVALID, "workspace_bytes <= 0");
+    const StartArgs sa{score, q_end, t_end};
+    const TraceArgs ta{q_start, t_start, cigar_offsets, cigar, cigar_len,
+                       static_cast<uint8_t *>(workspace), workspace_bytes};
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, nullptr, nullptr,
+                     nullptr, stream, opts, &sa, NMasks{nullptr, nullptr}, -1, &ta);
 }
 
 salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,

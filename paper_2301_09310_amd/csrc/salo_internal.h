@@ -79,6 +79,18 @@ struct KParams {
     const uint32_t *t_nmask;
     // banded pass: only cells with |i - j| <= band exist (-1: no band)
     int32_t band;
+    // trace pass (with in_score / in_qend / in_tend): the answers' starts;
+    // the pass aligns q[q_start..q_end] against t[t_start..t_end], keeps a
+    // 4-bit choice code per cell in trace_ws (trace_slot bytes per block)
+    // and writes each pair's CIGAR runs to cig[cig_off[p] ..], their count
+    // to cig_len[p] (nullptr cig: not the trace pass)
+    const int32_t *in_qstart;
+    const int32_t *in_tstart;
+    uint8_t *trace_ws;
+    int64_t trace_slot;
+    const int64_t *cig_off;
+    uint32_t *cig;
+    int32_t *cig_len;
     int32_t force_int32;
     int32_t packed_ok;             // scoring admits 16-bit packed cells
     int32_t half_ok;               // scoring admits binary16 cells (and no_f16 is off)

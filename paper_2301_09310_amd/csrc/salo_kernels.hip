@@ -192,7 +192,9 @@ struct PairRef {
 // answer (q_end, t_end): m = q_end + 1, n = t_end + 1, and q0 / t0 are the
 // stream positions of the reversed sequences' first bases (q_end, t_end);
 // a pair with forward score 0 is empty.
-template <bool REV>
+// TR (trace pass): the span q[q_start..q_end] x t[t_start..t_end] of the
+// pair's answer; a pair with score 0 is empty.
+template <bool REV, bool TR = false>
 __device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, int64_t pos_end,
                                              bool present) {
     PairRef r{0, 0, 0, 0, -1, false};
@@ -215,6 +217,15 @@ __device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, int6
             return r;
         }
         r.q0 = q0 + qe; r.t0 = t0 + te; r.m = qe + 1; r.n = te + 1;
+    } else if constexpr (TR) {
+        const int32_t sc = P.in_score[p], qe = P.in_qend[p], te = P.in_tend[p];
+        const int32_t qs = P.in_qstart[p], ts = P.in_tstart[p];
+        if (sc <= 0) return r;
+        if (qs < 0 || qs > qe || qe >= m || ts < 0 || ts > te || te >= n) {
+            r.invalid = true;
+            return r;
+        }
+        r.q0 = q0 + qs; r.t0 = t0 + ts; r.m = qe - qs + 1; r.n = te - ts + 1;
     } else {
         r.q0 = q0; r.t0 = t0; r.m = (int32_t)m; r.n = (int32_t)n;
     }
@@ -274,6 +285,104 @@ __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr
     P.out_tend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF)) : -1;
 }
 
+// Trace pass: choice codes, one nibble per cell, as the fill stores them.
+// Bits 0-1: where H came from (0 diagonal with unequal bases, 3 diagonal
+// with equal bases, 1 E, 2 F), taking the diagonal, then E, then F when
+// several give H; bit 2: E extends E(i, j-1) (0: it opens from H(i, j-1),
+// preferred on equal values); bit 3: F extends F(i-1, j) likewise.
+constexpr uint32_t kTrDiagX = 0, kTrDiagEq = 3, kTrE = 1, kTrF = 2;
+constexpr uint32_t kOpEq = 7, kOpX = 8, kOpI = 1, kOpD = 2;   // BAM codes
+
+// Walk the codes back from the pair's last cell (its answer's end) to its
+// first (the start) and write the CIGAR runs in alignment order.  Runs on
+// one lane per group.  Within the span every optimal local path begins at
+// the start with positive prefix scores, so along the path the local
+// recurrence (0 floor, E and F clamped at 0) makes the same choices as the
+// anchored one the oracle runs.  key: the group's best cell, which must be
+// the span's last cell with the pair's score.
+template <int K>
+__device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
+                           const uint8_t *codes, bool fits, int W) {
+    if (pr.id < 0) return;
+    const int64_t p = pr.id;
+    const int32_t want = P.in_score[p];
+    auto fail = [&](int32_t code) {
+        P.cig_len[p] = code;
+        atomicAdd(P.errors, 1ull);
+    };
+    if (pr.invalid) return fail(-1);
+    if (want <= 0) {
+        P.cig_len[p] = 0;
+        return;
+    }
+    if (!fits) return fail(-2);
+    const int32_t s = (int32_t)(key >> 32);
+    const int32_t col = (int32_t)(0xFFFFu - (uint32_t)(key & 0xFFFF));
+    const int32_t row = (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF));
+    if (s != want || row != pr.n - 1 || col != pr.m - 1) return fail(-1);
+    const int64_t base = P.cig_off[p];
+    const int64_t cap = P.cig_off[p + 1] - base;
+    uint32_t *out = P.cig + base;
+    const int WK = W * K;
+    int i = pr.n - 1, j = pr.m - 1, state = 0;   // 0: H, 1: E, 2: F
+    uint32_t run_op = 0, run_len = 0;
+    int64_t nruns = 0;
+    bool ok = true;
+    // every op takes one step and every switch into a gap state another
+    for (int64_t guard = 0; guard <= 2 * ((int64_t)pr.m + pr.n) + 4; ++guard) {
+        if (i < 0 || j < 0) {
+            ok = false;
+            break;
+        }
+        const int c = j / WK, rem = j - c * WK, lq = rem / K, k = rem - lq * K;
+        const uint8_t byte =
+            codes[((int64_t)(c * W + lq) * pr.n + i) * (K / 2) + (k >> 1)];
+        const uint32_t nib = (byte >> ((k & 1) * 4)) & 15u;
+        uint32_t op;
+        bool done = false;
+        if (state == 0) {
+            const uint32_t src = nib & 3u;
+            if (src == kTrE) { state = 1; continue; }
+            if (src == kTrF) { state = 2; continue; }
+            op = src == kTrDiagEq ? kOpEq : kOpX;
+            done = i == 0 && j == 0;
+            --i;
+            --j;
+        } else if (state == 1) {
+            op = kOpI;
+            if (!((nib >> 2) & 1u)) state = 0;
+            --j;
+        } else {
+            op = kOpD;
+            if (!((nib >> 3) & 1u)) state = 0;
+            --i;
+        }
+        if (op == run_op) {
+            ++run_len;
+        } else {
+            if (run_len > 0) {
+                if (nruns >= cap) { ok = false; break; }
+                out[nruns++] = (run_len << 4) | run_op;
+            }
+            run_op = op;
+            run_len = 1;
+        }
+        if (done) {
+            if (nruns >= cap) { ok = false; break; }
+            out[nruns++] = (run_len << 4) | run_op;
+            run_len = 0;
+            break;
+        }
+    }
+    if (!ok || run_len != 0) return fail(-1);
+    for (int64_t a = 0, b = nruns - 1; a < b; ++a, --b) {
+        const uint32_t x = out[a];
+        out[a] = out[b];
+        out[b] = x;
+    }
+    P.cig_len[p] = (int32_t)nruns;
+}
+
 // Cell types of a unit: 32-bit integers (one pair per group), or two pairs
 // per group in the 16-bit halves of every register, as saturating 16-bit
 // integers or as binary16 numbers.
@@ -294,7 +403,7 @@ enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
 // of (below) the band only ever sees the boundary's E (F), and one right
 // of (above) it only feeds other out-of-band cells -- with H = 0 the
 // in-band cells see exactly the boundary values of the restricted table.
-template <int K, int CT, bool REV, bool NM, bool BAND>
+template <int K, int CT, bool REV, bool NM, bool BAND, bool TR>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                          BaseStream qm, BaseStream tm,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
@@ -304,6 +413,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     constexpr int NPG = PK ? 2 : 1;
     static_assert(K % 4 == 0 && K <= 32, "K must be 4..32, multiple of 4");
     static_assert(!(BAND && (REV || NM)), "the banded pass is forward, without N masks");
+    static_assert(!TR || (CT == kCellWide && !REV && !NM && !BAND),
+                  "the trace pass runs 32-bit cells, forward, without masks or band");
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / W;          // W is a power of two
     const int l = lane & (W - 1);
@@ -312,7 +423,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     PairRef pr[NPG];
 #pragma unroll
     for (int h = 0; h < NPG; ++h)
-        pr[h] = load_pair<REV>(P, pos0 + (int64_t)g * NPG + h, pos_end, mine);
+        pr[h] = load_pair<REV, TR>(P, pos0 + (int64_t)g * NPG + h, pos_end, mine);
 
     int rmax = 0, mmax = 0;
 #pragma unroll
@@ -362,6 +473,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
     const Slot bslot{slot};
+    // trace pass: this group's share of the block's code slot; the pair's
+    // codes take (its chunks) x W lanes x n rows x K/2 bytes, laid out
+    // [chunk][lane][row] so that a lane's consecutive rows are adjacent
+    uint8_t *tr_codes = nullptr;
+    bool tr_fits = false;
+    int tr_chunks = 0;
+    if constexpr (TR) {
+        const int64_t gslot = (P.trace_slot / G) & ~(int64_t)15;
+        tr_chunks = (pr[0].m + W * K - 1) / (W * K);
+        tr_fits = (int64_t)tr_chunks * W * pr[0].n * (K / 2) <= gslot;
+        tr_codes = P.trace_ws + (int64_t)blockIdx.x * P.trace_slot + (int64_t)g * gslot;
+    }
     // slot byte offsets: row r of this lane's group is at (r & rwrap) *
     // row_bytes + ld_lane; a row past the rows the previous chunk wrote
     // reads as 0 through the descriptor's range check (rows below 64 Ki and
@@ -468,6 +591,14 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             F[k] = 0;
         }
         uint32_t hprev = 0;           // H(i-1, col0-1)
+        // trace pass: bit k = F of the next row's column k extends (F(i+1, j)
+        // != H(i, j) - alpha), and where this lane's codes of the chunk go
+        uint32_t fbits = 0;
+        uint8_t *tr_lane = nullptr;
+        if constexpr (TR) {
+            if (tr_fits && mine && c < tr_chunks)
+                tr_lane = tr_codes + (int64_t)(c * W + l) * pr[0].n * (K / 2);
+        }
         uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
         uint32_t cbest = 0;           // packed (or wide) best row maximum in this chunk
         int32_t crow[NPG];
@@ -641,15 +772,44 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     for (int k = K - 1; k >= 0; --k)
                         H[k] = (uint32_t)((int)(k > 0 ? H[k - 1] : hd) +
                                           (SEL[k] == tb ? a : b));
+                    uint32_t code[TR ? K / 8 : 1];
+                    uint32_t fnext = 0;
+#pragma unroll
+                    for (int w = 0; w < (TR ? K / 8 : 1); ++w) code[w] = 0;
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const int f = (int)F[k];
-                        const int hh = max3i((int)H[k], f, (int)e) & (int)inband(k);
+                        const int dv = (int)H[k];
+                        const int hh = max3i(dv, f, (int)e) & (int)inband(k);
+                        if constexpr (TR) {
+                            // H(i, j-1): this row's value of the column to the left
+                            const int hl = k > 0 ? (int)H[k - 1] : (int)hin;
+                            uint32_t nib = hh == dv ? (SEL[k] == tb ? kTrDiagEq : kTrDiagX)
+                                                    : (hh == (int)e ? kTrE : kTrF);
+                            nib |= (int)e != hl - alpha ? 4u : 0u;
+                            nib |= ((fbits >> k) & 1u) << 3;
+                            code[k >> 3] |= nib << (4 * (k & 7));
+                        }
                         H[k] = (uint32_t)hh;
                         const int ha = hh - alpha;
                         F[k] = (uint32_t)max3i(f - beta, ha, 0);
+                        if constexpr (TR) fnext |= ((int)F[k] != ha ? 1u : 0u) << k;
                         rowmax = k == 0 ? (uint32_t)hh : (uint32_t)max((int)rowmax, hh);
                         e = (uint32_t)max3i((int)e - beta, ha, 0);
+                    }
+                    if constexpr (TR) {
+                        fbits = fnext;
+                        if (tr_lane != nullptr && (uint32_t)i < (uint32_t)pr[0].n) {
+                            uint8_t *dst = tr_lane + (int64_t)i * (K / 2);
+                            if constexpr (K == 8) {
+                                *reinterpret_cast<uint32_t *>(dst) = code[0];
+                            } else if constexpr (K == 16) {
+                                *reinterpret_cast<uint2 *>(dst) = make_uint2(code[0], code[1]);
+                            } else {
+                                *reinterpret_cast<uint4 *>(dst) =
+                                    make_uint4(code[0], code[1], code[2], code[3]);
+                            }
+                        }
                     }
                 }
                 hprev = hin;
@@ -736,14 +896,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
     for (int h = 0; h < NPG; ++h) {
         const uint64_t key = group_max_u64(best[h].key(), W);
-        if (l == 0 && mine) write_result<REV>(P, pr[h], key);
+        if constexpr (TR) {
+            if (l == 0 && mine) trace_walk<K>(P, pr[h], key, tr_codes, tr_fits, W);
+        } else {
+            if (l == 0 && mine) write_result<REV>(P, pr[h], key);
+        }
     }
 }
 
 // The narrowest cell type every pair of the unit admits.
 template <bool REV>
 __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, int npairs) {
-    if (!P.packed_ok || P.force_int32) return kCellWide;
+    if (!P.packed_ok || P.force_int32 || P.cig != nullptr) return kCellWide;
     const int lane = threadIdx.x & (kWave - 1);
     bool ok16 = true, okh = P.half_ok != 0;
     for (int k = lane; k < npairs; k += kWave) {
@@ -759,7 +923,7 @@ __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, in
     return __builtin_amdgcn_readfirstlane(all16 ? (allh ? kCellF16 : kCellU16) : kCellWide);
 }
 
-template <int K, bool REV, bool NM, bool BAND>
+template <int K, bool REV, bool NM, bool BAND, bool TR>
 __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                              BaseStream qm, BaseStream tm,
                                              int64_t pos0, int npairs, int W, uint32_t *slot,
@@ -769,7 +933,7 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     int rmax = 0;
     const int lane = threadIdx.x & (kWave - 1);
     for (int k = lane; k < npairs; k += kWave) {
-        const PairRef r = load_pair<REV>(P, pos0 + k, pos0 + npairs, true);
+        const PairRef r = load_pair<REV, TR>(P, pos0 + k, pos0 + npairs, true);
         rmax = max(rmax, r.n);
     }
     const int R = wave_max(rmax);
@@ -783,21 +947,24 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     const int passes = (G + fit - 1) / fit;
     // with N masks the host turns binary16 cells off (their table cannot
     // give an N column the mismatch), so NM never instantiates them
-    const int ct = unit_cell_type<REV>(P, pos0, npairs);
-    if (!NM && ct == kCellF16) {
-        if constexpr (!NM) {
+    const int ct = TR ? (int)kCellWide : unit_cell_type<REV>(P, pos0, npairs);
+    if (!NM && !TR && ct == kCellF16) {
+        if constexpr (!NM && !TR) {
             for (int ps = 0; ps < passes; ++ps)
-                run_unit<K, kCellF16, REV, false, BAND>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
+                run_unit<K, kCellF16, REV, false, BAND, false>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
                                                   ps * fit, min(fit, G - ps * fit), W, slot, lds);
         }
-    } else if (ct == kCellU16 || ct == kCellF16) {
-        for (int ps = 0; ps < passes; ++ps)
-            run_unit<K, kCellU16, REV, NM, BAND>(P, qs, ts, qm, tm, pos0, pos0 + npairs, ps * fit,
-                                           min(fit, G - ps * fit), W, slot, lds);
+    } else if (!TR && (ct == kCellU16 || ct == kCellF16)) {
+        if constexpr (!TR) {
+            for (int ps = 0; ps < passes; ++ps)
+                run_unit<K, kCellU16, REV, NM, BAND, false>(P, qs, ts, qm, tm, pos0,
+                                                            pos0 + npairs, ps * fit,
+                                                            min(fit, G - ps * fit), W, slot, lds);
+        }
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;
-            run_unit<K, kCellWide, REV, NM, BAND>(P, qs, ts, qm, tm, pos0 + (int64_t)half * G,
+            run_unit<K, kCellWide, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0 + (int64_t)half * G,
                                             pos0 + npairs, ps * fit, min(fit, G - ps * fit), W,
                                             slot, lds);
         }
@@ -806,9 +973,11 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
 
 // Resident waves per SIMD each width is compiled for: 512 VGPRs per lane
 // hold three waves of at most 168 registers (K <= 16) or two of at most 256
-// (K = 32, and every kernel that reads N masks).  The host sizes the grid
-// to match.
-template <int K, bool NM = false> constexpr int kMinWaves = (K <= 16 && !NM) ? 3 : 2;
+// (K = 32, and every kernel that reads N masks).  The trace pass keeps
+// three only at K = 8 (its choice codes take registers of their own).  The
+// host sizes the grid to match.
+template <int K, bool NM = false, bool TR = false>
+constexpr int kMinWaves = TR ? (K <= 8 ? 3 : 2) : ((K <= 16 && !NM) ? 3 : 2);
 
 // Plain mode: pairs in input order, fixed lanes/cols, units of 128/W pairs
 // dealt to waves round robin.
@@ -826,7 +995,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pos0 = u * ppu;
         const int np = (int)min<int64_t>(ppu, P.n_pairs - pos0);
-        process_unit<K, false, NM, false>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved);
+        process_unit<K, false, NM, false, false>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved);
     }
 }
 
@@ -836,9 +1005,9 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
 // width comes from the unit's bin; the query columns per lane (K) are fixed
 // per launch so every width shares one register budget.  REV is the start
 // pass (reversed prefixes ending at the forward answers); NM reads N masks;
-// BAND restricts the table to a diagonal band.
-template <int K, bool REV, bool NM, bool BAND>
-__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM>, 8))) void persistent_kernel(KParams P) {
+// BAND restricts the table to a diagonal band; TR is the trace pass.
+template <int K, bool REV, bool NM, bool BAND, bool TR>
+__global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM, TR>, 8))) void persistent_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
     BaseStream qs, ts, qm, tm;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
@@ -866,7 +1035,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
         const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
         const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
-        process_unit<K, REV, NM, BAND>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved);
+        process_unit<K, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved);
     }
 }
 
@@ -901,17 +1070,21 @@ bool persistent_lanes_supported(int lanes) {
            lanes == 64;
 }
 
-template <bool REV, bool NM, bool BAND = false>
+template <bool REV, bool NM, bool BAND = false, bool TR = false>
 hipError_t launch_persistent_t(const KParams &p, int cols, int grid, hipStream_t stream) {
-    if (cols == 32)
-        hipLaunchKernelGGL((persistent_kernel<32, REV, NM, BAND>), dim3(grid), dim3(kWave), 0,
-                           stream, p);
-    else if (cols == 16)
-        hipLaunchKernelGGL((persistent_kernel<16, REV, NM, BAND>), dim3(grid), dim3(kWave), 0,
-                           stream, p);
+    // the trace pass has no 32-column kernel (its codes would spill)
+    if (cols == 32) {
+        if constexpr (!TR)
+            hipLaunchKernelGGL((persistent_kernel<32, REV, NM, BAND, TR>), dim3(grid),
+                               dim3(kWave), 0, stream, p);
+        else
+            return hipErrorInvalidValue;
+    } else if (cols == 16)
+        hipLaunchKernelGGL((persistent_kernel<16, REV, NM, BAND, TR>), dim3(grid), dim3(kWave),
+                           0, stream, p);
     else if (cols == 8)
-        hipLaunchKernelGGL((persistent_kernel<8, REV, NM, BAND>), dim3(grid), dim3(kWave), 0,
-                           stream, p);
+        hipLaunchKernelGGL((persistent_kernel<8, REV, NM, BAND, TR>), dim3(grid), dim3(kWave),
+                           0, stream, p);
     else
         return hipErrorInvalidValue;
     return hipGetLastError();
@@ -922,6 +1095,10 @@ hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t s
     if (p.band >= 0) {
         if (nm || p.in_score) return hipErrorInvalidValue;
         return launch_persistent_t<false, false, true>(p, cols, grid, stream);
+    }
+    if (p.cig != nullptr) {
+        if (nm || !p.in_score || !p.in_qstart || cols == 32) return hipErrorInvalidValue;
+        return launch_persistent_t<false, false, false, true>(p, cols, grid, stream);
     }
     if (p.in_score)
         return nm ? launch_persistent_t<true, true>(p, cols, grid, stream)

@@ -38,6 +38,14 @@ __device__ __forceinline__ PairLen pair_len(const KParams &P, int64_t p) {
     const bool valid = m >= 0 && n >= 0 && m <= SALO_MAX_LEN_DEV && n <= SALO_MAX_LEN_DEV &&
                        q0 >= 0 && t0 >= 0;
     if (!valid) return {0, 0};
+    if (P.in_qstart) {
+        // trace pass: the span from the answer's start to its end
+        const int32_t sc = P.in_score[p], qe = P.in_qend[p], te = P.in_tend[p];
+        const int32_t qs = P.in_qstart[p], ts = P.in_tstart[p];
+        if (sc <= 0 || qs < 0 || qs > qe || qe >= m || ts < 0 || ts > te || te >= n)
+            return {0, 0};
+        return {(int64_t)qe - qs + 1, (int64_t)te - ts + 1};
+    }
     if (P.in_score) {
         // start pass: the reversed prefixes ending at the forward answer
         const int32_t sc = P.in_score[p], qe = P.in_qend[p], te = P.in_tend[p];

@@ -92,6 +92,9 @@ def load(path: str | None = None):
         lib.salo_align_batch_banded.argtypes = [vp, vp, vp, vp, i64, Scoring, i32, vp, vp, vp,
                                                 vp, ctypes.POINTER(Options)]
         lib.salo_align_batch_banded.restype = i32
+        lib.salo_align_trace.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp, vp,
+                                         vp, vp, vp, i64, vp, ctypes.POINTER(Options)]
+        lib.salo_align_trace.restype = i32
         if path is None:
             _lib = lib
         return lib
@@ -205,6 +208,51 @@ def align_banded(q_seqs, q_offsets, t_seqs, t_offsets, band: int, scoring=(1, -4
                                      _stream_handle(stream), ctypes.byref(opts))
     _check(lib, st)
     return out
+
+
+CIGAR_OPS = {7: "=", 8: "X", 1: "I", 2: "D"}
+
+
+def cigar_offsets(q_offsets, t_offsets):
+    """Device int64 offsets giving each pair room for m + n CIGAR runs."""
+    import torch
+    cap = (q_offsets[1:] - q_offsets[:-1]) + (t_offsets[1:] - t_offsets[:-1])
+    off = torch.zeros(cap.numel() + 1, dtype=torch.int64, device=q_offsets.device)
+    torch.cumsum(cap, 0, out=off[1:])
+    return off
+
+
+def align_trace(q_seqs, q_offsets, t_seqs, t_offsets, answers, starts, scoring=(1, -4, 6, 1),
+                cig_off=None, workspace=None, workspace_bytes=1 << 30, stream=None, **options):
+    """CIGAR of every pair's best alignment (salo_align_trace).
+    answers: (score, q_end, t_end) of align_batch; starts: (q_start,
+    t_start) of align_starts.  Returns (cig_off, cig, cig_len): int64
+    offsets, uint32 runs (as int32 storage), int32 run counts, all CUDA.
+    workspace: a CUDA uint8 tensor (allocated with workspace_bytes if None)."""
+    import torch
+    lib = load()
+    n = _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets)
+    arrs = (answers[0], starts[0], answers[1], starts[1], answers[2])
+    for t in arrs:
+        if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != n:
+            raise ValueError("answers and starts must be contiguous int32 CUDA tensors")
+    dev = q_offsets.device
+    if cig_off is None:
+        cig_off = cigar_offsets(q_offsets, t_offsets)
+    total = int(cig_off[-1].item()) if n > 0 else 0
+    cig = torch.zeros(max(total, 1), dtype=torch.int32, device=dev)
+    cig_len = torch.empty(max(n, 0), dtype=torch.int32, device=dev)
+    if workspace is None:
+        workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=dev)
+    sc = Scoring(*[int(x) for x in scoring])
+    opts = make_options(**options)
+    st = lib.salo_align_trace(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                              t_offsets.data_ptr(), n, sc, *(x.data_ptr() for x in arrs),
+                              cig_off.data_ptr(), cig.data_ptr(), cig_len.data_ptr(),
+                              workspace.data_ptr(), workspace.numel(), _stream_handle(stream),
+                              ctypes.byref(opts))
+    _check(lib, st)
+    return cig_off, cig, cig_len
 
 
 def align_starts(q_seqs, q_offsets, t_seqs, t_offsets, answers, scoring=(1, -4, 6, 1),

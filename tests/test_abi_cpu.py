@@ -31,7 +31,8 @@ def test_header_declares_the_boundary():
     for n in ["salo_align_batch", "salo_align_batch_ex", "salo_reserve",
               "salo_error_count", "salo_last_timing", "salo_set_bins", "salo_get_bins",
               "salo_last_error", "salo_release", "salo_version", "salo_pack_bases",
-              "salo_align_starts", "salo_align_batch_n", "salo_align_batch_banded"]:
+              "salo_align_starts", "salo_align_batch_n", "salo_align_batch_banded",
+              "salo_align_trace"]:
         assert n in names
 
 
@@ -185,3 +186,29 @@ def test_banded_validation(lib):
     p = salo.make_options(mode="plain")
     assert f(ADDR, ADDR, ADDR, ADDR, 5, SC, 5, ADDR, ADDR, ADDR, NULL, ctypes.byref(p)) == -5
     assert "persistent" in lib.salo_last_error().decode()
+
+
+def test_trace_validation(lib):
+    o = salo.make_options()
+    f = salo.load().salo_align_trace
+    A = ADDR
+
+    wsbuf = ctypes.create_string_buffer(1024)
+    WS = (ctypes.addressof(wsbuf) + 255) & ~255
+
+    def call(n=5, ans=A, off=A, cig=A, ws=WS, wsb=1 << 20, opts=o):
+        return f(A, A, A, A, n, SC, ans, ans, ans, ans, ans, off, cig, A, ws, wsb, NULL,
+                 ctypes.byref(opts))
+    assert f(None, None, None, None, 0, SC, None, None, None, None, None, None, None, None,
+             None, 0, NULL, ctypes.byref(o)) == 0
+    assert call(ans=None) == -1
+    assert call(ans=A + 2) == -1
+    assert call(off=A + 4) == -1
+    assert call(cig=A + 2) == -1
+    assert call(ws=None) == -1
+    assert call(ws=WS + 16) == -1
+    assert "256-byte" in lib.salo_last_error().decode()
+    assert call(wsb=0) == -1
+    assert call(opts=salo.make_options(mode="plain")) == -5
+    assert call(opts=salo.make_options(cols=32)) == -5
+    assert call(n=-1) == -1

@@ -271,3 +271,13 @@ def test_planted_mistake_is_caught(name):
     with tempfile.TemporaryDirectory() as tmp:
         assert _passes_all(_mutant(src, tmp, "real"))
         assert not _passes_all(_mutant(src.replace(old, new), tmp, name))
+
+
+def test_threaded_calls_agree():
+    b = I.random_pairs(33, 90, 150, related=0.8)
+    s, qs, qe, ts, te = answers(b, (1, -4, 6, 1))
+    one = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, s, qs, qe, ts, te)
+    many = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, s, qs, qe, ts, te,
+                         threads=6)
+    for x, y in zip(one, many):
+        assert np.array_equal(x, y)
