@@ -232,8 +232,9 @@ salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_of
  * whose runs do not fit, -2 for a pair too large for its share of the
  * workspace; -1 and -2 are counted, see salo_error_count).
  * workspace: DEVICE scratch of workspace_bytes, 256-byte aligned, owned by
- * the caller and only used during the call.  Each resident wave (CUs x 12
- * with 8 columns per lane, CUs x 8 with 16) gets an equal share; a wave
+ * the caller and only used during the call.  Each resident wave (CUs x 8
+ * with the default 16 columns per lane, CUs x 12 with opts->cols = 8)
+ * gets an equal share; a wave
  * aligns up to 64 / W spans at once (W lanes per span, 4..64 by span
  * length) and each needs ceil(span length / (W x cols)) x W x cols x
  * (span rows) / 2 bytes of it.  Too small for 4 KiB per wave:

@@ -286,8 +286,9 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     const bool nm = masks.q != nullptr || masks.t != nullptr;
     // query columns per lane: 16, or 8 for a banded pass with a band of at
     // most 160 (measured: the narrower chunks it allows waste fewer cells)
-    // (the trace pass: 8 columns by default, 2 waves per SIMD at 16)
-    const int cols_default = ((band >= 0 && band <= 160) || trace) ? 8 : 16;
+    // (the trace pass: 16 columns, at 2 waves per SIMD, measured faster
+    // than 8 at 3: 41.6 vs 51.6 ms for its fill on short reads)
+    const int cols_default = (band >= 0 && band <= 160) ? 8 : 16;
     const int cols_req = o.cols ? o.cols : cols_default;
     const int wpc = o.waves_per_cu ? o.waves_per_cu
                                    : (cols_req >= 32 || nm || (trace && cols_req > 8) ? 8 : 12);
