@@ -716,16 +716,20 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         (uint32_t)i < (uint32_t)pr[0].n ? (MM4 ^ (XM << (bA << 3))) : 0u;
                     const uint32_t TB =
                         (uint32_t)i < (uint32_t)pr[1].n ? (MM4 ^ (XM << (bB << 3))) : 0u;
-                    // diagonal terms in place, last column first (each
-                    // H[k] still holds row i-1 when column k+1 reads it)
-#pragma unroll
-                    for (int k = K - 1; k >= 0; --k)
-                        H[k] = hadd(k > 0 ? H[k - 1] : hd,
-                                    __builtin_amdgcn_perm(TB, TA, SEL[k]));
+                    // the diagonal term of column k+1 is formed in column
+                    // k's step, from H[k] before it takes row i: it is
+                    // independent of the E chain (hh, ha, e), so it fills
+                    // the gap gfx950 needs between two packed instructions
+                    // when the second reads the first's result
+                    uint32_t dk = hadd(hd, __builtin_amdgcn_perm(TB, TA, SEL[0]));
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
+                        const uint32_t dnext =
+                            k + 1 < K ? hadd(H[k], __builtin_amdgcn_perm(TB, TA, SEL[k + 1]))
+                                      : 0u;
                         const uint32_t f = F[k];
-                        const uint32_t hh = pmax3(H[k], f, e) & inband(k);
+                        const uint32_t hh = pmax3(dk, f, e) & inband(k);
+                        dk = dnext;
                         H[k] = hh;
                         const uint32_t ha = hadd(hh, NAL2);
                         F[k] = hmax(hadd(f, NBE2), ha);
@@ -746,15 +750,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     }
                     const uint32_t TA = okA ? (KC << (bA << 3)) : 0u;
                     const uint32_t TB = okB ? (KC << (bB << 3)) : 0u;
-#pragma unroll
-                    for (int k = K - 1; k >= 0; --k)
-                        H[k] = psub(padd(k > 0 ? H[k - 1] : hd,
-                                         __builtin_amdgcn_perm(TB, TA, SEL[k])),
-                                    NB2);
+                    // diagonal term of column k+1 formed in column k's
+                    // step, as in the binary16 loop
+                    uint32_t dk = psub(padd(hd, __builtin_amdgcn_perm(TB, TA, SEL[0])), NB2);
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
+                        const uint32_t dnext =
+                            k + 1 < K ? psub(padd(H[k], __builtin_amdgcn_perm(TB, TA, SEL[k + 1])),
+                                             NB2)
+                                      : 0u;
                         const uint32_t f = F[k];
-                        const uint32_t hh = pmax3(H[k], f, e) & inband(k);
+                        const uint32_t hh = pmax3(dk, f, e) & inband(k);
+                        dk = dnext;
                         H[k] = hh;
                         const uint32_t ha = psub(hh, AL2);
                         F[k] = pmax(psub(f, BE2), ha);
@@ -811,6 +818,13 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             }
                         }
                     }
+                }
+                if constexpr (CT != kCellWide) {
+                    // keep the F updates in this block, among the E chain's
+                    // independent work, rather than sunk below the row save
+                    // where each add and max pair would stall
+#pragma unroll
+                    for (int k = 0; k < K; ++k) asm volatile("" ::"v"(F[k]));
                 }
                 hprev = hin;
                 hout = H[K - 1];
