@@ -209,30 +209,27 @@ struct TraceArgs {
     int64_t ws_bytes;
 };
 
-// Bins of the trace pass (32-bit cells, 8 columns per lane by default):
-// lane-group width by span length so that a chunk of W x 8 columns covers
-// short spans without padding and long spans run on whole waves.
+// Bins of the trace pass, for each cell kind: lane-group width by span
+// length so that a chunk of W x cols columns covers short spans without
+// padding and long spans run on whole waves.
 BinTable trace_bin_table(int cols, int forced_lanes) {
     BinTable bt;
     std::memset(&bt, 0, sizeof bt);
     const int32_t hi[] = {4 * cols, 8 * cols, 16 * cols, 32 * cols, 65535};
     const int32_t lanes[] = {4, 8, 16, 32, 64};
-    int32_t prev = 0;
-    for (int b = 0; b < 5; ++b) {
-        bt.m_lo[b] = prev;
-        bt.m_hi[b] = hi[b];
-        prev = hi[b];
-        bt.packed[b] = 0;
-        bt.lanes[b] = forced_lanes ? forced_lanes : lanes[b];
-        bt.cols[b] = cols;
+    int n = 0;
+    for (int kind = 1; kind >= 0; --kind) {
+        int32_t prev = 0;
+        for (int b = 0; b < 5; ++b, ++n) {
+            bt.m_lo[n] = prev;
+            bt.m_hi[n] = hi[b];
+            prev = hi[b];
+            bt.packed[n] = kind;
+            bt.lanes[n] = forced_lanes ? forced_lanes : lanes[b];
+            bt.cols[n] = cols;
+        }
     }
-    // the plan expects a bin of each kind; no trace pair is 16-bit
-    bt.m_lo[5] = 0;
-    bt.m_hi[5] = 65535;
-    bt.packed[5] = 1;
-    bt.lanes[5] = 64;
-    bt.cols[5] = cols;
-    bt.n_bins = 6;
+    bt.n_bins = n;
     return bt;
 }
 
@@ -326,8 +323,7 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
         p.cig_off = trace->cig_off;
         p.cig = trace->cig;
         p.cig_len = trace->cig_len;
-        p.force_int32 = 1;
-        p.half_ok = 0;
+        p.half_ok = 0;                 // choice bits need integer cells
     }
     // binary16 cells cannot give an N column the mismatch: off with masks
     p.half_ok = !o.no_f16 && !nm && scoring_half_ok(scoring.match, scoring.mismatch,

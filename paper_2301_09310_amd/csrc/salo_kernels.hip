@@ -57,6 +57,15 @@ __device__ __forceinline__ uint32_t padd(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t pmax(uint32_t a, uint32_t b) {
     return as_u(__builtin_elementwise_max(as_v(a), as_v(b)));
 }
+// a * b + c in both halves (v_pk_mad_u16)
+__device__ __forceinline__ uint32_t pmad(uint32_t a, uint32_t b, uint32_t c) {
+    return as_u(as_v(a) * as_v(b) + as_v(c));
+}
+// 1 in each half that is non-zero, else 0
+__device__ __forceinline__ uint32_t pnz(uint32_t a) {
+    const u16x2 one = {1, 1};
+    return as_u(__builtin_elementwise_min(as_v(a), one));
+}
 // Maximum of three packed cell pairs.  Cell values stay in [0, 0x7BFF]
 // (kPackedLimit), where reading the bits as binary16 gives finite,
 // non-negative numbers (denormals included, which the kernels keep) in the
@@ -286,11 +295,16 @@ __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr
 }
 
 // Trace pass: choice codes, one nibble per cell, as the fill stores them.
-// Bits 0-1: where H came from (0 diagonal with unequal bases, 3 diagonal
-// with equal bases, 1 E, 2 F), taking the diagonal, then E, then F when
-// several give H; bit 2: E extends E(i, j-1) (0: it opens from H(i, j-1),
-// preferred on equal values); bit 3: F extends F(i-1, j) likewise.
-constexpr uint32_t kTrDiagX = 0, kTrDiagEq = 3, kTrE = 1, kTrF = 2;
+// Bit 0: H is not the diagonal term; bit 1: H is not E (so the walk takes
+// the diagonal, then E, then F, whichever first gives H); bit 2: E extends
+// E(i, j-1) rather than opening from H(i, j-1) (open is taken on equal
+// values); bit 3: F extends F(i-1, j) likewise.  Every bit is "a != b"
+// for values with a >= b, which 16-bit unsigned cells compute as
+// min(a - b, 1) in both halves at once.
+// Layouts, per group and chunk, [lane][row] so that a lane's rows are
+// adjacent: 32-bit cells keep K/2 bytes per row, cell k in byte k/2 at bit
+// 4 (k & 1); 16-bit cells keep K bytes per row for the group's two pairs,
+// cell k in 32-bit word k/4, pair h in half h, at bit 4 (3 - (k & 3)).
 constexpr uint32_t kOpEq = 7, kOpX = 8, kOpI = 1, kOpD = 2;   // BAM codes
 
 // Walk the codes back from the pair's last cell (its answer's end) to its
@@ -300,9 +314,10 @@ constexpr uint32_t kOpEq = 7, kOpX = 8, kOpI = 1, kOpD = 2;   // BAM codes
 // recurrence (0 floor, E and F clamped at 0) makes the same choices as the
 // anchored one the oracle runs.  key: the group's best cell, which must be
 // the span's last cell with the pair's score.
-template <int K>
+template <int K, bool PKD>
 __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
-                           const uint8_t *codes, bool fits, int W) {
+                           const uint8_t *codes, bool fits, int W, int half, int rows,
+                           BaseStream qs, BaseStream ts) {
     if (pr.id < 0) return;
     const int64_t p = pr.id;
     const int32_t want = P.in_score[p];
@@ -335,16 +350,33 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
             break;
         }
         const int c = j / WK, rem = j - c * WK, lq = rem / K, k = rem - lq * K;
-        const uint8_t byte =
-            codes[((int64_t)(c * W + lq) * pr.n + i) * (K / 2) + (k >> 1)];
-        const uint32_t nib = (byte >> ((k & 1) * 4)) & 15u;
+        // in state H the step may be an aligned pair: fetch both bases with
+        // the code, so the three loads overlap
+        const int64_t qp = pr.q0 + j, tp = pr.t0 + i;
+        uint32_t qword = 0, tword = 0;
+        if (state == 0) {
+            qword = qs.word(qp >> 4);
+            tword = ts.word(tp >> 4);
+        }
+        uint32_t nib;
+        if constexpr (PKD) {
+            const uint32_t w = *reinterpret_cast<const uint32_t *>(
+                codes + ((int64_t)(c * W + lq) * rows + i) * K + 4 * (k >> 2));
+            nib = (w >> (16 * half + 4 * (3 - (k & 3)))) & 15u;
+        } else {
+            const uint8_t byte = codes[((int64_t)(c * W + lq) * rows + i) * (K / 2) + (k >> 1)];
+            nib = (byte >> ((k & 1) * 4)) & 15u;
+        }
         uint32_t op;
         bool done = false;
         if (state == 0) {
-            const uint32_t src = nib & 3u;
-            if (src == kTrE) { state = 1; continue; }
-            if (src == kTrF) { state = 2; continue; }
-            op = src == kTrDiagEq ? kOpEq : kOpX;
+            if (nib & 1u) {
+                state = (nib & 2u) ? 2 : 1;
+                continue;
+            }
+            const uint32_t qb = (qword >> (2 * (qp & 15))) & 3u;
+            const uint32_t tb = (tword >> (2 * (tp & 15))) & 3u;
+            op = qb == tb ? kOpEq : kOpX;
             done = i == 0 && j == 0;
             --i;
             --j;
@@ -413,8 +445,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     constexpr int NPG = PK ? 2 : 1;
     static_assert(K % 4 == 0 && K <= 32, "K must be 4..32, multiple of 4");
     static_assert(!(BAND && (REV || NM)), "the banded pass is forward, without N masks");
-    static_assert(!TR || (CT == kCellWide && !REV && !NM && !BAND),
-                  "the trace pass runs 32-bit cells, forward, without masks or band");
+    static_assert(!TR || (CT != kCellF16 && !REV && !NM && !BAND),
+                  "the trace pass runs integer cells, forward, without masks or band");
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / W;          // W is a power of two
     const int l = lane & (W - 1);
@@ -476,13 +508,22 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     // trace pass: this group's share of the block's code slot; the pair's
     // codes take (its chunks) x W lanes x n rows x K/2 bytes, laid out
     // [chunk][lane][row] so that a lane's consecutive rows are adjacent
+    // (16-bit cells: the group's two pairs share K bytes per lane and row,
+    // over the larger pair's chunks and rows)
     uint8_t *tr_codes = nullptr;
     bool tr_fits = false;
-    int tr_chunks = 0;
+    int tr_chunks = 0, tr_rows = 0;
+    constexpr int kTrRowBytes = PK ? K : K / 2;
     if constexpr (TR) {
         const int64_t gslot = (P.trace_slot / G) & ~(int64_t)15;
-        tr_chunks = (pr[0].m + W * K - 1) / (W * K);
-        tr_fits = (int64_t)tr_chunks * W * pr[0].n * (K / 2) <= gslot;
+        int mg = 0;
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) {
+            mg = max(mg, pr[h].m);
+            tr_rows = max(tr_rows, pr[h].n);
+        }
+        tr_chunks = (mg + W * K - 1) / (W * K);
+        tr_fits = (int64_t)tr_chunks * W * tr_rows * kTrRowBytes <= gslot;
         tr_codes = P.trace_ws + (int64_t)blockIdx.x * P.trace_slot + (int64_t)g * gslot;
     }
     // slot byte offsets: row r of this lane's group is at (r & rwrap) *
@@ -591,13 +632,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             F[k] = 0;
         }
         uint32_t hprev = 0;           // H(i-1, col0-1)
-        // trace pass: bit k = F of the next row's column k extends (F(i+1, j)
-        // != H(i, j) - alpha), and where this lane's codes of the chunk go
+        // trace pass: whether F of the next row's columns extends (F(i+1, j)
+        // != H(i, j) - alpha) -- 32-bit cells: bit k; 16-bit cells: bit 0 of
+        // each cell's nibble, in the code words' layout -- and where this
+        // lane's codes of the chunk go
         uint32_t fbits = 0;
+        uint32_t facc[TR && PK ? K / 4 : 1];
+#pragma unroll
+        for (int w = 0; w < (TR && PK ? K / 4 : 1); ++w) facc[w] = 0;
         uint8_t *tr_lane = nullptr;
         if constexpr (TR) {
             if (tr_fits && mine && c < tr_chunks)
-                tr_lane = tr_codes + (int64_t)(c * W + l) * pr[0].n * (K / 2);
+                tr_lane = tr_codes + (int64_t)(c * W + l) * tr_rows * kTrRowBytes;
         }
         uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
         uint32_t cbest = 0;           // packed (or wide) best row maximum in this chunk
@@ -753,6 +799,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     // diagonal term of column k+1 formed in column k's
                     // step, as in the binary16 loop
                     uint32_t dk = psub(padd(hd, __builtin_amdgcn_perm(TB, TA, SEL[0])), NB2);
+                    // trace pass: code words of this row, and the F bits
+                    // for the next one
+                    uint32_t acc[TR ? K / 4 : 1], fnew[TR ? K / 4 : 1];
+                    uint32_t ha_left = 0;          // H(i, j-1) - alpha
+                    if constexpr (TR) {
+#pragma unroll
+                        for (int w = 0; w < K / 4; ++w) {
+                            acc[w] = 0;
+                            fnew[w] = 0;
+                        }
+                        ha_left = psub(hin, AL2);
+                    }
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const uint32_t dnext =
@@ -761,14 +819,43 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                       : 0u;
                         const uint32_t f = F[k];
                         const uint32_t hh = pmax3(dk, f, e) & inband(k);
+                        if constexpr (TR) {
+                            // H >= the diagonal term and >= E; E >= H(i, j-1) - alpha
+                            const uint32_t nd = pnz(psub(hh, dk));
+                            const uint32_t ne = pnz(psub(hh, e));
+                            const uint32_t ex = pnz(psub(e, ha_left));
+                            const uint32_t nib = pmad(ex, 0x00040004u, pmad(ne, 0x00020002u, nd));
+                            acc[k >> 2] = pmad(acc[k >> 2], 0x00100010u, nib);
+                        }
                         dk = dnext;
                         H[k] = hh;
                         const uint32_t ha = psub(hh, AL2);
                         F[k] = pmax(psub(f, BE2), ha);
+                        if constexpr (TR) {
+                            // F(i+1, j) >= H(i, j) - alpha
+                            fnew[k >> 2] = pmad(fnew[k >> 2], 0x00100010u, pnz(psub(F[k], ha)));
+                            ha_left = ha;
+                        }
                         e = pmax(psub(e, BE2), ha);
                         // row maximum two columns at a time
                         if (k & 1)
                             rowmax = k == 1 ? pmax(H[0], hh) : pmax3(rowmax, H[k - 1], hh);
+                    }
+                    if constexpr (TR) {
+#pragma unroll
+                        for (int w = 0; w < K / 4; ++w) {
+                            acc[w] |= facc[w] << 3;    // bit 0 of each nibble to bit 3
+                            facc[w] = fnew[w];
+                        }
+                        if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
+                            uint8_t *dst = tr_lane + (int64_t)i * kTrRowBytes;
+                            if constexpr (K == 8) {
+                                *reinterpret_cast<uint2 *>(dst) = make_uint2(acc[0], acc[1]);
+                            } else {
+                                *reinterpret_cast<uint4 *>(dst) =
+                                    make_uint4(acc[0], acc[1], acc[2], acc[3]);
+                            }
+                        }
                     }
                 } else {
                     bool okt = (uint32_t)i < (uint32_t)pr[0].n;
@@ -791,8 +878,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         if constexpr (TR) {
                             // H(i, j-1): this row's value of the column to the left
                             const int hl = k > 0 ? (int)H[k - 1] : (int)hin;
-                            uint32_t nib = hh == dv ? (SEL[k] == tb ? kTrDiagEq : kTrDiagX)
-                                                    : (hh == (int)e ? kTrE : kTrF);
+                            uint32_t nib = hh != dv ? 1u : 0u;
+                            nib |= hh != (int)e ? 2u : 0u;
                             nib |= (int)e != hl - alpha ? 4u : 0u;
                             nib |= ((fbits >> k) & 1u) << 3;
                             code[k >> 3] |= nib << (4 * (k & 7));
@@ -806,8 +893,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     }
                     if constexpr (TR) {
                         fbits = fnext;
-                        if (tr_lane != nullptr && (uint32_t)i < (uint32_t)pr[0].n) {
-                            uint8_t *dst = tr_lane + (int64_t)i * (K / 2);
+                        if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
+                            uint8_t *dst = tr_lane + (int64_t)i * kTrRowBytes;
                             if constexpr (K == 8) {
                                 *reinterpret_cast<uint32_t *>(dst) = code[0];
                             } else if constexpr (K == 16) {
@@ -911,7 +998,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     for (int h = 0; h < NPG; ++h) {
         const uint64_t key = group_max_u64(best[h].key(), W);
         if constexpr (TR) {
-            if (l == 0 && mine) trace_walk<K>(P, pr[h], key, tr_codes, tr_fits, W);
+            // one walker per pair: lane h of the group (lane 0 for both
+            // pairs of a one-lane group)
+            if (mine && l == (W > 1 ? h : 0))
+                trace_walk<K, PK>(P, pr[h], key, tr_codes, tr_fits, W, h, tr_rows, qs, ts);
         } else {
             if (l == 0 && mine) write_result<REV>(P, pr[h], key);
         }
@@ -921,7 +1011,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 // The narrowest cell type every pair of the unit admits.
 template <bool REV>
 __device__ __forceinline__ int unit_cell_type(const KParams &P, int64_t pos0, int npairs) {
-    if (!P.packed_ok || P.force_int32 || P.cig != nullptr) return kCellWide;
+    if (!P.packed_ok || P.force_int32) return kCellWide;
     const int lane = threadIdx.x & (kWave - 1);
     bool ok16 = true, okh = P.half_ok != 0;
     for (int k = lane; k < npairs; k += kWave) {
@@ -961,20 +1051,19 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     const int passes = (G + fit - 1) / fit;
     // with N masks the host turns binary16 cells off (their table cannot
     // give an N column the mismatch), so NM never instantiates them
-    const int ct = TR ? (int)kCellWide : unit_cell_type<REV>(P, pos0, npairs);
+    // the trace pass has binary16 cells off (half_ok = 0)
+    const int ct = unit_cell_type<REV>(P, pos0, npairs);
     if (!NM && !TR && ct == kCellF16) {
         if constexpr (!NM && !TR) {
             for (int ps = 0; ps < passes; ++ps)
                 run_unit<K, kCellF16, REV, false, BAND, false>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
                                                   ps * fit, min(fit, G - ps * fit), W, slot, lds);
         }
-    } else if (!TR && (ct == kCellU16 || ct == kCellF16)) {
-        if constexpr (!TR) {
-            for (int ps = 0; ps < passes; ++ps)
-                run_unit<K, kCellU16, REV, NM, BAND, false>(P, qs, ts, qm, tm, pos0,
-                                                            pos0 + npairs, ps * fit,
-                                                            min(fit, G - ps * fit), W, slot, lds);
-        }
+    } else if (ct == kCellU16 || ct == kCellF16) {
+        for (int ps = 0; ps < passes; ++ps)
+            run_unit<K, kCellU16, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
+                                                     ps * fit, min(fit, G - ps * fit), W, slot,
+                                                     lds);
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;

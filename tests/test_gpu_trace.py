@@ -79,6 +79,19 @@ def test_random_pairs(dev, scoring):
     check(I.random_pairs(41, 400, 300, min_len=0, related=0.8), "random", scoring=scoring)
 
 
+@pytest.mark.parametrize("scoring", [(1, -4, 6, 1), (3, -2, 0, 2)])
+def test_forced_32bit_cells(dev, scoring):
+    check(I.random_pairs(44, 300, 300, min_len=0, related=0.8), "int32", scoring=scoring,
+          force_int32=True)
+
+
+def test_mixed_cell_kinds(dev):
+    """match 16 puts the long pairs above the 16-bit bound: units of both
+    kinds in one call."""
+    b = I.random_pairs(45, 200, 2500, min_len=1, related=0.9)
+    check(b, "mixed kinds", scoring=(16, -20, 30, 5), workspace_bytes=16 << 30)
+
+
 @pytest.mark.parametrize("cols", [8, 16])
 @pytest.mark.parametrize("lanes", [0, 4, 64])
 def test_widths(dev, cols, lanes):
