@@ -601,7 +601,11 @@ def trace_bench(args) -> int:
 
     kern_ms = float(np.mean(dp_ms))
     achieved = OPS_PER_CELL * span / (kern_ms * 1e-3) / 1e12
-    peak = PEAK_TOPS["i32"]
+    # 16-bit integer cells where a pair's span admits them (no binary16)
+    smn = np.minimum(a_np[1] - s_np[0] + 1, a_np[2] - s_np[1] + 1)[pos]
+    u16 = SCORING[0] * (smn + 1) - SCORING[1] <= 0x7BFF
+    dtype = "u16x2" if u16.all() else ("u16x2+i32" if u16.any() else "i32")
+    peak = PEAK_TOPS["u16x2"] if u16.any() else PEAK_TOPS["i32"]
     roof = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3),
             "unit": "TOP/s", "frac": round(achieved / peak, 4),
             "traffic": measured_traffic("trace_" + args.workload),
@@ -632,7 +636,7 @@ def trace_bench(args) -> int:
         "metric": "GCUPS over the start-to-end spans (bit-exact CIGAR vs oracle), trace pass",
         "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1, "steps": args.steps,
         "warmup": max(args.warmup, 1), "ms_per_step": round(ms, 4), "higher_is_better": True,
-        "scaling": "weak", "vs_baseline": None, "dtype": "i32", "data": "synthetic",
+        "scaling": "weak", "vs_baseline": None, "dtype": dtype, "data": "synthetic",
         "config": {"workload": args.workload, "pairs": n, "span_cells": span,
                    "cigar_runs": runs, "scoring": list(SCORING), "lanes": args.lanes,
                    "cols": args.cols, "workspace_gb": args.trace_workspace_gb,
