@@ -143,7 +143,7 @@ def main(argv=None) -> int:
                     help="time the banded pass (cells with |i - j| <= W) instead")
     ap.add_argument("--trace", action="store_true",
                     help="time the trace pass (CIGAR of each best alignment) instead")
-    ap.add_argument("--trace-workspace-gb", type=float, default=4.0)
+    ap.add_argument("--trace-workspace-gb", type=float, default=16.0)
     ap.add_argument("--pack", action="store_true",
                     help="time the on-device packing of the workload's reads written as "
                          "characters (forward and reverse-complement)")

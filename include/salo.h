@@ -235,11 +235,13 @@ salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_of
  * the caller and only used during the call.  Each resident wave (CUs x 8
  * with the default 16 columns per lane, CUs x 12 with opts->cols = 8)
  * gets an equal share; a wave
- * aligns up to 64 / W pair groups at once (W lanes per group, 4..64 by
- * span length; a group holds two pairs in 16-bit cells or one in 32-bit
- * cells) and each group needs ceil(its longer span / (W x cols)) x W x cols
- * x (its longer span's rows) / 2 bytes of it per pair.  Too small for
- * 4 KiB per wave: SALO_ERR_INVALID.
+ * aligns up to 64 / W pair groups at once (a group holds two pairs in
+ * 16-bit cells or one in 32-bit cells) and each group needs ceil(its
+ * longer span / (W x cols)) x W x cols x (its longer span's rows) / 2 bytes
+ * of it per pair.  W (2..64 lanes) grows with the span length, and with
+ * opts->lanes = 0 also until a span length class fits the workspace, so a
+ * larger workspace gives narrower, faster groups.  Too small for 4 KiB per
+ * wave: SALO_ERR_INVALID.
  * Runs in the persistent mode with 16-bit integer cells where the score
  * bound allows and 32-bit cells elsewhere (opts->force_int32 forces the
  * latter; opts->mode = SALO_MODE_PLAIN or opts->cols = 32 return

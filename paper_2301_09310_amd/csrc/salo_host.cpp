@@ -209,23 +209,31 @@ struct TraceArgs {
     int64_t ws_bytes;
 };
 
-// Bins of the trace pass, for each cell kind: lane-group width by span
-// length so that a chunk of W x cols columns covers short spans without
-// padding and long spans run on whole waves.
-BinTable trace_bin_table(int cols, int forced_lanes) {
+// Bins of the trace pass, for each cell kind, by span length.  Narrow
+// lane groups put more pairs on a wave, and a wave walks its pairs' traces
+// together, so they hide the walk's load latency best (measured on
+// MI355X, short reads: 2 lanes 32.0 ms, 4 lanes 33.7, 16 lanes 47.1).
+// But a wave's share of the workspace is split among its 64 / W groups, so
+// a bin's width is raised until its longest span (rows taken as 1.5 x its
+// length) fits a group's share: 0.5 B per cell and pair.
+BinTable trace_bin_table(int cols, int forced_lanes, int64_t slot_bytes) {
     BinTable bt;
     std::memset(&bt, 0, sizeof bt);
-    const int32_t hi[] = {4 * cols, 8 * cols, 16 * cols, 32 * cols, 65535};
-    const int32_t lanes[] = {4, 8, 16, 32, 64};
+    const int32_t hi[] = {16 * cols, 64 * cols, 256 * cols, 65535};
+    const int32_t pref[] = {2, 8, 32, 64};
     int n = 0;
     for (int kind = 1; kind >= 0; --kind) {
         int32_t prev = 0;
-        for (int b = 0; b < 5; ++b, ++n) {
+        for (int b = 0; b < 4; ++b, ++n) {
+            int w = pref[b];
+            const double cells = 1.5 * (double)hi[b] * (double)hi[b];
+            const double group_bytes = cells * (kind ? 1.0 : 0.5);   // two pairs or one
+            while (w < 64 && (64.0 / w) * group_bytes > (double)slot_bytes) w <<= 1;
             bt.m_lo[n] = prev;
             bt.m_hi[n] = hi[b];
             prev = hi[b];
             bt.packed[n] = kind;
-            bt.lanes[n] = forced_lanes ? forced_lanes : lanes[b];
+            bt.lanes[n] = forced_lanes ? forced_lanes : w;
             bt.cols[n] = cols;
         }
     }
@@ -369,7 +377,7 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     st = ensure_plan(*ws, n_pairs, stream);
     if (st != SALO_OK) return st;
     const BinTable bt =
-        trace ? trace_bin_table(cols, o.lanes)
+        trace ? trace_bin_table(cols, o.lanes, p.trace_slot)
               : make_bin_table(cols, o.lanes ? o.lanes
                                              : (band >= 0 ? band_lanes(band, cols, n_pairs, grid)
                                                           : 0));

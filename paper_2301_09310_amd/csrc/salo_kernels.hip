@@ -338,7 +338,9 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
     const int64_t base = P.cig_off[p];
     const int64_t cap = P.cig_off[p + 1] - base;
     uint32_t *out = P.cig + base;
-    const int WK = W * K;
+    // W and K are powers of two: column j is in chunk j >> log2(W K), lane
+    // (j >> log2 K) & (W - 1), slot j & (K - 1)
+    const int lw = __builtin_ctz((unsigned)W), lk = __builtin_ctz((unsigned)K);
     int i = pr.n - 1, j = pr.m - 1, state = 0;   // 0: H, 1: E, 2: F
     uint32_t run_op = 0, run_len = 0;
     int64_t nruns = 0;
@@ -349,7 +351,7 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
             ok = false;
             break;
         }
-        const int c = j / WK, rem = j - c * WK, lq = rem / K, k = rem - lq * K;
+        const int c = j >> (lw + lk), lq = (j >> lk) & (W - 1), k = j & (K - 1);
         // in state H the step may be an aligned pair: fetch both bases with
         // the code, so the three loads overlap
         const int64_t qp = pr.q0 + j, tp = pr.t0 + i;

@@ -124,19 +124,18 @@ def test_long_spans(dev):
 
 
 def test_small_workspace_marks_large_pairs(dev):
-    # 4 KiB per wave (CUs x 8 waves at 16 columns per lane): short spans
-    # fit, long ones are reported (-2) and
-    # counted; the rest are still exact
+    # 200 KB per wave (CUs x 8 waves at 16 columns per lane): short spans
+    # fit, long ones are reported (-2) and counted; the rest are still exact
     import torch
     n_cus = torch.cuda.get_device_properties(0).multi_processor_count
     b = I.random_pairs(43, 300, 400, min_len=1, related=0.9)
-    ans, st, off, cig, ln, errors = gpu_trace(b, workspace_bytes=n_cus * 8 * 4096)
+    ans, st, off, cig, ln, errors = gpu_trace(b, workspace_bytes=n_cus * 8 * 200 * 1024)
     w_ans = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets)
     w_st = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *w_ans)
     _, wcig, wln = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, w_ans[0],
                                  w_st[0], w_ans[1], w_st[1], w_ans[2])
     big = ln == -2
-    assert big.any() and errors == int(big.sum())
+    assert big.any() and (~big & (wln > 0)).any() and errors == int(big.sum())
     ok = ~big
     assert np.array_equal(ln[ok], wln[ok])
     for p in np.nonzero(ok & (wln > 0))[0]:
