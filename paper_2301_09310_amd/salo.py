@@ -223,12 +223,15 @@ def cigar_offsets(q_offsets, t_offsets):
 
 
 def align_trace(q_seqs, q_offsets, t_seqs, t_offsets, answers, starts, scoring=(1, -4, 6, 1),
-                cig_off=None, workspace=None, workspace_bytes=1 << 30, stream=None, **options):
+                cig_off=None, workspace=None, workspace_bytes=1 << 30, stream=None, out=None,
+                **options):
     """CIGAR of every pair's best alignment (salo_align_trace).
     answers: (score, q_end, t_end) of align_batch; starts: (q_start,
     t_start) of align_starts.  Returns (cig_off, cig, cig_len): int64
     offsets, uint32 runs (as int32 storage), int32 run counts, all CUDA.
-    workspace: a CUDA uint8 tensor (allocated with workspace_bytes if None)."""
+    workspace: a CUDA uint8 tensor (allocated with workspace_bytes if None).
+    out: (cig, cig_len) to fill; with cig_off and workspace also given, the
+    call allocates nothing and does not synchronise (graph capture)."""
     import torch
     lib = load()
     n = _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets)
@@ -239,9 +242,15 @@ def align_trace(q_seqs, q_offsets, t_seqs, t_offsets, answers, starts, scoring=(
     dev = q_offsets.device
     if cig_off is None:
         cig_off = cigar_offsets(q_offsets, t_offsets)
-    total = int(cig_off[-1].item()) if n > 0 else 0
-    cig = torch.zeros(max(total, 1), dtype=torch.int32, device=dev)
-    cig_len = torch.empty(max(n, 0), dtype=torch.int32, device=dev)
+    if out is None:
+        total = int(cig_off[-1].item()) if n > 0 else 0
+        cig = torch.zeros(max(total, 1), dtype=torch.int32, device=dev)
+        cig_len = torch.empty(max(n, 0), dtype=torch.int32, device=dev)
+    else:
+        cig, cig_len = out
+        if cig.dtype != torch.int32 or cig_len.dtype != torch.int32 or \
+                not cig.is_contiguous() or cig_len.numel() != n:
+            raise ValueError("out must be (int32 cig, int32 cig_len of n_pairs) CUDA tensors")
     if workspace is None:
         workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=dev)
     sc = Scoring(*[int(x) for x in scoring])

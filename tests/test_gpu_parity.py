@@ -331,3 +331,67 @@ def test_graph_capture_replays(dev):
         torch.cuda.synchronize()
         got = tuple(x.cpu().numpy().astype(np.int64) for x in out)
         assert_same(src, got, want1 if rep % 2 == 0 else want2, "replay %d" % rep)
+
+
+def test_graph_capture_all_passes(dev):
+    """Forward, start, trace and banded calls captured together in one HIP
+    graph: every replay, on alternating inputs of the same shapes with eager
+    work in between, equals the oracles."""
+    import torch
+    from paper_2301_09310_amd import salo
+    b1 = I.random_pairs(52, 1500, 500, related=0.7)
+    b2 = I.Batch(b1.q_seqs ^ np.uint8(0x55), b1.q_offsets, b1.t_seqs, b1.t_offsets)
+    wants = []
+    for b in (b1, b2):
+        a = oracle_align(b)
+        st = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *a)
+        tr = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, a[0], st[0], a[1],
+                           st[1], a[2])
+        bd = O.align_banded(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, 40)
+        wants.append((a, st, tr, bd))
+    n = b1.n_pairs
+    s = torch.cuda.Stream()
+    q, qo, t, to = salo.to_device(b1)
+    i32 = lambda: torch.empty(n, dtype=torch.int32, device="cuda")
+    ans, sts, band = (i32(), i32(), i32()), (i32(), i32()), (i32(), i32(), i32())
+    cig_off = salo.cigar_offsets(qo, to)
+    cig = torch.zeros(int(cig_off[-1].item()), dtype=torch.int32, device="cuda")
+    cig_len = i32()
+    ws = torch.empty(1 << 30, dtype=torch.uint8, device="cuda")
+
+    def calls():
+        salo.align_batch(q, qo, t, to, out=ans, stream=s)
+        salo.align_starts(q, qo, t, to, ans, out=sts, stream=s)
+        salo.align_trace(q, qo, t, to, ans, sts, cig_off=cig_off, workspace=ws,
+                         out=(cig, cig_len), stream=s)
+        salo.align_banded(q, qo, t, to, 40, out=band, stream=s)
+    with torch.cuda.stream(s):
+        salo.reserve(n, stream=s)
+        calls()                                        # warm-up on the capture stream
+    s.synchronize()
+    assert salo.error_count(s) == 0
+    _say("graph capture of all passes")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        calls()
+    off = cig_off.cpu().numpy()
+    for rep in range(4):
+        src = b1 if rep % 2 == 0 else b2
+        a, st, (woff, wcig, wln), bd = wants[rep % 2]
+        for x, y in zip((q, qo, t, to), salo.to_device(src)):
+            x.copy_(y)
+        for o in ans + sts + band + (cig_len,):
+            o.fill_(-7)                                # eager work between replays
+        torch.cuda.synchronize()
+        _say("graph replay", rep)
+        g.replay()
+        torch.cuda.synchronize()
+        cpu = lambda x: x.cpu().numpy().astype(np.int64)
+        for got, want in ((ans, a), (sts, st), (band, bd)):
+            for x, y in zip(got, want):
+                assert np.array_equal(cpu(x), y), "replay %d" % rep
+        ln = cpu(cig_len)
+        assert np.array_equal(ln, wln), "replay %d" % rep
+        cg = cig.cpu().numpy().view(np.uint32)
+        for p in np.nonzero(wln > 0)[0]:
+            assert np.array_equal(cg[off[p]:off[p] + ln[p]], wcig[woff[p]:woff[p] + wln[p]])
