@@ -146,7 +146,7 @@ salo_status_t salo_align_batch_ex(const uint8_t *q_seqs, const int64_t *q_offset
  * ceil(offsets[n_pairs] / 32) words; either may be NULL (no N in that
  * stream).  An N scores `mismatch` against every base, N included.  With a
  * mask the 16-bit integer and 32-bit cells are used (binary16 cells are
- * off) and the default grid is 8 waves per CU.
+ * off).
  */
 salo_status_t salo_align_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
                                  const int64_t *q_offsets, const uint8_t *t_seqs,

@@ -287,7 +287,6 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
 
     // resident waves per CU at the kernel's register budget: 3 per SIMD for
     // 8 or 16 query columns per lane, 2 per SIMD for 32
-    // (kernels that read N masks are compiled for 2 per SIMD)
     const bool nm = masks.q != nullptr || masks.t != nullptr;
     // query columns per lane: 16, or 8 for a banded pass with a band of at
     // most 160 (measured: the narrower chunks it allows waste fewer cells)
@@ -296,7 +295,7 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     const int cols_default = (band >= 0 && band <= 160) ? 8 : 16;
     const int cols_req = o.cols ? o.cols : cols_default;
     const int wpc = o.waves_per_cu ? o.waves_per_cu
-                                   : (cols_req >= 32 || nm || (trace && cols_req > 8) ? 8 : 12);
+                                   : (cols_req >= 32 || (trace && cols_req > 8) ? 8 : 12);
     const int64_t grid = (int64_t)ws->cus * wpc;
     st = ensure_slots(*ws, grid, stream);
     if (st != SALO_OK) return st;

@@ -1077,12 +1077,12 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
 }
 
 // Resident waves per SIMD each width is compiled for: 512 VGPRs per lane
-// hold three waves of at most 168 registers (K <= 16) or two of at most 256
-// (K = 32, and every kernel that reads N masks).  The trace pass keeps
-// three only at K = 8 (its choice codes take registers of their own).  The
-// host sizes the grid to match.
+// hold three waves of at most 168 registers (K <= 16, N masks included) or
+// two of at most 256 (K = 32).  The trace pass keeps three only at K = 8
+// (its choice codes take registers of their own).  The host sizes the grid
+// to match.
 template <int K, bool NM = false, bool TR = false>
-constexpr int kMinWaves = TR ? (K <= 8 ? 3 : 2) : ((K <= 16 && !NM) ? 3 : 2);
+constexpr int kMinWaves = TR ? (K <= 8 ? 3 : 2) : (K <= 16 ? 3 : 2);
 
 // Plain mode: pairs in input order, fixed lanes/cols, units of 128/W pairs
 // dealt to waves round robin.
