@@ -21,7 +21,11 @@ namespace salo {
 namespace {
 
 constexpr int kPackThreads = 256;
-constexpr int kWin = 512;   // sequence offsets staged per block (revcomp)
+// reverse complement: words per thread (the block's sequence search and
+// offset staging are paid once for kRcWords * kPackThreads words) and
+// sequence offsets staged per block
+constexpr int kRcWords = 8;
+constexpr int kWin = 1024;
 
 // 2-bit code of a character and whether it is A, C, G or T in either case
 // (the code formula maps A/a->0, C/c->1, G/g->2, T/t->3).
@@ -158,11 +162,36 @@ __device__ __forceinline__ void gather16(const uint8_t *chars, int64_t n, int64_
     for (int i = 0; i < 4; ++i) g[i] = __builtin_amdgcn_alignbit(x[i + 1], x[i], sh);
 }
 
-__device__ __forceinline__ void seq_bounds(const int64_t *win, int64_t s0, const int64_t *off,
-                                           int64_t n_seqs, int64_t s, int64_t &lo,
-                                           int64_t &hi) {
+// Largest s in [0, n) with off[s] <= p (off non-decreasing), or -1.  The
+// 64 lanes of the calling wave probe 64 evenly spaced entries per round,
+// so the range shrinks 64-fold per dependent load (4 rounds for 2M
+// sequences, against 21 for a one-lane binary search).  Every lane of the
+// wave calls it and gets the answer.
+__device__ int64_t wave_last_le(const int64_t *off, int64_t n, int64_t p) {
+    const int lane = threadIdx.x & 63;
+    int64_t a = 0, b = n;   // answer = a - 1 + #{s in [a, b): off[s] <= p}
+    while (b - a > 64) {
+        const int64_t step = (b - a + 63) >> 6;
+        const int64_t idx = a + (int64_t)lane * step;
+        const bool t = idx < b && off[idx] <= p;
+        const int c = __popcll(__ballot(t));
+        if (c == 0) return a - 1;                 // off[a] > p; off[a-1] <= p
+        const int64_t na = a + (int64_t)(c - 1) * step;
+        b = min<int64_t>(b, a + (int64_t)c * step);
+        a = na;
+    }
+    const int64_t idx = a + lane;
+    const bool t = idx < b && off[idx] <= p;
+    return a - 1 + __popcll(__ballot(t));
+}
+
+// Bounds [lo, hi) of sequence s: from the block's staged offsets
+// (win[0 .. nwin) = off[s0 ..]) when they hold both, else from off.
+__device__ __forceinline__ void seq_bounds(const int64_t *win, int64_t s0, int nwin,
+                                           const int64_t *off, int64_t n_seqs, int64_t s,
+                                           int64_t &lo, int64_t &hi) {
     const int64_t j = s - s0;
-    if (j >= 0 && j + 1 <= kWin) {
+    if (j >= 0 && j + 1 < nwin) {
         lo = win[j];
         hi = win[j + 1];
     } else {
@@ -179,123 +208,136 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
                                                              uint32_t *n_mask,
                                                              unsigned long long *invalid) {
     __shared__ int64_t win[kWin + 1];
-    __shared__ int64_t s_first;
-    const int64_t w0 = (int64_t)blockIdx.x * kPackThreads;
+    __shared__ int64_t s_first, s_last;
+    constexpr int64_t kSpan = (int64_t)kRcWords * kPackThreads;   // words per block
+    const int64_t w0 = (int64_t)blockIdx.x * kSpan;
     const int64_t nw = (n + 15) >> 4;
-    if (threadIdx.x == 0) {
-        // sequence of the block's first base (off[0..n_seqs-1] are starts)
-        const int64_t s = n_seqs > 0 ? last_le(off, 0, n_seqs, w0 << 4) : -1;
-        s_first = s < 0 ? 0 : s;
+    // sequences of the block's first and last bases (off[0..n_seqs-1] are
+    // starts), one wave each
+    if (threadIdx.x < 64) {
+        const int64_t s = n_seqs > 0 ? wave_last_le(off, n_seqs, w0 << 4) : -1;
+        if (threadIdx.x == 0) s_first = s < 0 ? 0 : s;
+    } else if (threadIdx.x < 128) {
+        const int64_t p_end = min<int64_t>(n, (w0 + kSpan) << 4) - 1;
+        const int64_t s = n_seqs > 0 ? wave_last_le(off, n_seqs, p_end) : -1;
+        if (threadIdx.x == 64) s_last = s < 0 ? 0 : s;
     }
     __syncthreads();
     const int64_t s0 = s_first;
-    for (int t = threadIdx.x; t <= kWin; t += kPackThreads) {
+    // stage off[s0 .. s_last + 1]: the bounds of every sequence the block
+    // touches (at most kWin + 1 entries; beyond them, off is read directly)
+    const int nwin = (int)min<int64_t>(kWin + 1, max<int64_t>(s_last - s0 + 2, 1));
+    for (int t = threadIdx.x; t < nwin; t += kPackThreads) {
         const int64_t idx = s0 + t;
         win[t] = idx <= n_seqs ? off[idx] : INT64_MAX;
     }
     __syncthreads();
 
-    const int64_t w = w0 + threadIdx.x;
     uint32_t bad = 0;
-    uint32_t nb16 = 0;
-    if (w < nw) {
-        const int64_t p0 = w << 4;
-        uint32_t word = 0;
-        // sequence of the word's first base: window index, else the table
-        int64_t s;
-        {
-            int a = 0, b = kWin;
-            while (a < b) {
-                const int mid = (a + b) >> 1;
-                if (win[mid] <= p0) a = mid + 1;
-                else b = mid;
+    // word w0 + it * kPackThreads + threadIdx.x in round it: each round's
+    // stores are contiguous, and the pairs of store_nmask stay in one wave
+    for (int it = 0; it < kRcWords; ++it) {
+        const int64_t w = w0 + (int64_t)it * kPackThreads + threadIdx.x;
+        uint32_t nb16 = 0;
+        if (w < nw) {
+            const int64_t p0 = w << 4;
+            uint32_t word = 0;
+            // sequence of the word's first base: window index, else the table
+            int64_t s;
+            {
+                int a = 0, b = nwin;
+                while (a < b) {
+                    const int mid = (a + b) >> 1;
+                    if (win[mid] <= p0) a = mid + 1;
+                    else b = mid;
+                }
+                const int j = a - 1;
+                if (j >= 0 && j + 1 < nwin && p0 < win[j + 1]) s = s0 + j;
+                else s = n_seqs > 0 ? last_le(off, 0, n_seqs, p0) : -1;
             }
-            const int j = a - 1;
-            if (j >= 0 && p0 < win[j + 1]) s = s0 + j;
-            else s = n_seqs > 0 ? last_le(off, 0, n_seqs, p0) : -1;
-        }
-        bool fast = false;
-        if (s >= 0 && s < n_seqs && p0 + 16 <= n) {
-            int64_t lo, hi;
-            seq_bounds(win, s0, off, n_seqs, s, lo, hi);
-            if (lo <= p0 && p0 < hi) {
-                // output base k (p = p0 + k) of sequence s comes from
-                // chars[lo + hi - 1 - p]; the word's first kb bases lie in s
-                const int64_t kb = min<int64_t>(hi - p0, 16);
-                uint32_t g[4], h[4] = {0u, 0u, 0u, 0u};
-                const int64_t A = lo + hi - 1 - p0;
-                gather16(chars, n, A - 15, g);             // g byte 15-k = chars[A - k]
-                fast = true;
-                if (kb < 16) {
-                    // the rest must lie in sequence s + 1 (else three or
-                    // more sequences share the word: per-base path)
-                    int64_t lo2, hi2;
-                    if (s + 1 < n_seqs) {
-                        seq_bounds(win, s0, off, n_seqs, s + 1, lo2, hi2);
-                        if (lo2 == hi && hi2 - lo2 >= 16 - kb) {
-                            gather16(chars, n, lo2 + hi2 - 1 - p0 - 15, h);
+            bool fast = false;
+            if (s >= 0 && s < n_seqs && p0 + 16 <= n) {
+                int64_t lo, hi;
+                seq_bounds(win, s0, nwin, off, n_seqs, s, lo, hi);
+                if (lo <= p0 && p0 < hi) {
+                    // output base k (p = p0 + k) of sequence s comes from
+                    // chars[lo + hi - 1 - p]; the word's first kb bases lie in s
+                    const int64_t kb = min<int64_t>(hi - p0, 16);
+                    uint32_t g[4], h[4] = {0u, 0u, 0u, 0u};
+                    const int64_t A = lo + hi - 1 - p0;
+                    gather16(chars, n, A - 15, g);             // g byte 15-k = chars[A - k]
+                    fast = true;
+                    if (kb < 16) {
+                        // the rest must lie in sequence s + 1 (else three or
+                        // more sequences share the word: per-base path)
+                        int64_t lo2, hi2;
+                        if (s + 1 < n_seqs) {
+                            seq_bounds(win, s0, nwin, off, n_seqs, s + 1, lo2, hi2);
+                            if (lo2 == hi && hi2 - lo2 >= 16 - kb) {
+                                gather16(chars, n, lo2 + hi2 - 1 - p0 - 15, h);
+                            } else {
+                                fast = false;
+                            }
                         } else {
                             fast = false;
                         }
-                    } else {
-                        fast = false;
                     }
-                }
-                if (fast) {
-                    // merged byte j (= base 15 - j): from g for j >= 16 - kb
-                    const int t = 16 - (int)kb;
-#pragma unroll
-                    for (int i = 0; i < 4; ++i) {
-                        const int r = t - 4 * i;   // first byte of dword i taken from g
-                        const uint32_t mg = r <= 0 ? 0xFFFFFFFFu
-                                                   : (r >= 4 ? 0u : (0xFFFFFFFFu << (8 * r)));
-                        g[i] = (g[i] & mg) | (h[i] & ~mg);
-                    }
-                    // base k = complement of merged byte 15 - k: bases
-                    // 4q..4q+3 are dword 3-q with its bytes reversed
-#pragma unroll
-                    for (int q = 0; q < 4; ++q) {
-                        const uint32_t rev = __builtin_amdgcn_perm(0u, g[3 - q], 0x00010203u);
-                        uint32_t nb4 = 0;
-                        word |= pack4<true, NM>(rev, bad, &nb4) << (8 * q);
-                        nb16 |= nb4 << (4 * q);
+                    if (fast) {
+                        // merged byte j (= base 15 - j): from g for j >= 16 - kb
+                        const int t = 16 - (int)kb;
+    #pragma unroll
+                        for (int i = 0; i < 4; ++i) {
+                            const int r = t - 4 * i;   // first byte of dword i taken from g
+                            const uint32_t mg = r <= 0 ? 0xFFFFFFFFu
+                                                       : (r >= 4 ? 0u : (0xFFFFFFFFu << (8 * r)));
+                            g[i] = (g[i] & mg) | (h[i] & ~mg);
+                        }
+                        // base k = complement of merged byte 15 - k: bases
+                        // 4q..4q+3 are dword 3-q with its bytes reversed
+    #pragma unroll
+                        for (int q = 0; q < 4; ++q) {
+                            const uint32_t rev = __builtin_amdgcn_perm(0u, g[3 - q], 0x00010203u);
+                            uint32_t nb4 = 0;
+                            word |= pack4<true, NM>(rev, bad, &nb4) << (8 * q);
+                            nb16 |= nb4 << (4 * q);
+                        }
                     }
                 }
             }
-        }
-        if (!fast) {
-            // per base: tails, words spanning three or more sequences, and
-            // offsets that break the documented rule
-            word = 0;
-            nb16 = 0;
-            int64_t sc = s;
-            for (int k = 0; k < 16; ++k) {
-                const int64_t p = p0 + k;
-                if (p >= n) break;
-                int64_t lo = 0, hi = 0;
-                if (sc >= 0 && sc < n_seqs) seq_bounds(win, s0, off, n_seqs, sc, lo, hi);
-                while (sc >= 0 && sc + 1 < n_seqs && hi <= p) {
-                    ++sc;
-                    seq_bounds(win, s0, off, n_seqs, sc, lo, hi);
-                }
-                bool ok = false, isn = false;
-                uint32_t code = 0;
-                if (sc >= 0 && sc < n_seqs && lo <= p && p < hi) {
-                    const int64_t src = lo + hi - 1 - p;
-                    if (src >= 0 && src < n) {
-                        const uint32_t c = chars[src];
-                        code = 3u - char_code(c, ok);
-                        isn = NM && is_n_char(c);
+            if (!fast) {
+                // per base: tails, words spanning three or more sequences, and
+                // offsets that break the documented rule
+                word = 0;
+                nb16 = 0;
+                int64_t sc = s;
+                for (int k = 0; k < 16; ++k) {
+                    const int64_t p = p0 + k;
+                    if (p >= n) break;
+                    int64_t lo = 0, hi = 0;
+                    if (sc >= 0 && sc < n_seqs) seq_bounds(win, s0, nwin, off, n_seqs, sc, lo, hi);
+                    while (sc >= 0 && sc + 1 < n_seqs && hi <= p) {
+                        ++sc;
+                        seq_bounds(win, s0, nwin, off, n_seqs, sc, lo, hi);
                     }
+                    bool ok = false, isn = false;
+                    uint32_t code = 0;
+                    if (sc >= 0 && sc < n_seqs && lo <= p && p < hi) {
+                        const int64_t src = lo + hi - 1 - p;
+                        if (src >= 0 && src < n) {
+                            const uint32_t c = chars[src];
+                            code = 3u - char_code(c, ok);
+                            isn = NM && is_n_char(c);
+                        }
+                    }
+                    bad += (ok || isn) ? 0u : 1u;
+                    word |= (ok ? code : 0u) << (2 * k);
+                    nb16 |= (isn ? 1u : 0u) << k;
                 }
-                bad += (ok || isn) ? 0u : 1u;
-                word |= (ok ? code : 0u) << (2 * k);
-                nb16 |= (isn ? 1u : 0u) << k;
             }
+            out[w] = word;
         }
-        out[w] = word;
+        if constexpr (NM) store_nmask(n_mask, w, nw, nb16);
     }
-    if constexpr (NM) store_nmask(n_mask, w, nw, nb16);
     add_invalid(invalid, bad);
 }
 
@@ -311,8 +353,10 @@ hipError_t launch_pack_t(const uint8_t *chars, int64_t n_chars, const int64_t *o
     if (blocks > 0x7FFFFFFFll) return hipErrorInvalidValue;
     uint32_t *out = reinterpret_cast<uint32_t *>(packed);
     if (revcomp)
-        hipLaunchKernelGGL((pack_revcomp<NM>), dim3((uint32_t)blocks), dim3(kPackThreads), 0,
-                           stream, chars, n_chars, offsets, n_seqs, out, n_mask, invalid);
+        hipLaunchKernelGGL((pack_revcomp<NM>),
+                           dim3((uint32_t)((blocks + kRcWords - 1) / kRcWords)),
+                           dim3(kPackThreads), 0, stream, chars, n_chars, offsets, n_seqs, out,
+                           n_mask, invalid);
     else if ((reinterpret_cast<uintptr_t>(chars) & 15) == 0)
         hipLaunchKernelGGL((pack_forward<true, NM>), dim3((uint32_t)blocks), dim3(kPackThreads),
                            0, stream, chars, n_chars, out, n_mask, invalid);

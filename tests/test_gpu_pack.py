@@ -27,10 +27,15 @@ def _say(*a):
     print("[case]", *a, flush=True)
 
 
-def _gpu_pack(chars, off, rc):
+def _gpu_pack(chars, off, rc, shift=0):
     import torch
     from paper_2301_09310_amd import salo
     c = torch.from_numpy(np.ascontiguousarray(chars, np.uint8)).cuda()
+    if shift:
+        # a view `shift` bytes into a larger buffer: 4-byte aligned, not 16
+        buf = torch.zeros(chars.size + 16, dtype=torch.uint8, device="cuda")
+        buf[shift:shift + chars.size] = c
+        c = buf[shift:shift + chars.size]
     o = torch.from_numpy(np.ascontiguousarray(off, np.int64)).cuda()
     inv = torch.zeros(1, dtype=torch.int64, device="cuda")
     # output buffer pre-filled with garbage: every byte must be written
@@ -41,10 +46,11 @@ def _gpu_pack(chars, off, rc):
     return out.cpu().numpy()[:nbytes], int(inv.item())
 
 
-def _check(chars, off, label):
+def _check(chars, off, label, shift=0):
     for rc in (False, True):
-        _say(label, "revcomp" if rc else "forward", "n_chars", chars.size, "n_seqs", off.size - 1)
-        got, bad = _gpu_pack(chars, off, rc)
+        _say(label, "revcomp" if rc else "forward", "n_chars", chars.size, "n_seqs",
+             off.size - 1, "shift", shift)
+        got, bad = _gpu_pack(chars, off, rc, shift)
         want, wbad = O.pack(chars, off, revcomp=rc)
         diff = np.nonzero(got != want)[0]
         assert diff.size == 0, "%s rc=%s: first differing byte %d gpu %02x oracle %02x" % (
@@ -125,3 +131,11 @@ def test_pack_then_align(dev):
     want = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets)
     for g, w, name in zip(res, want, ("score", "q_end", "t_end")):
         assert np.array_equal(g.cpu().numpy().astype(np.int64), w), name
+
+
+@pytest.mark.parametrize("shift", [4, 8, 12])
+def test_buffer_not_16_byte_aligned(dev, shift):
+    """The dword-gather kernels (a character buffer that is 4- but not
+    16-byte aligned) against the oracle, on ragged reads with invalid bases."""
+    chars, off = _random_case(91 + shift, 500, 400, noise=0.02)
+    _check(chars, off, "unaligned", shift=shift)
