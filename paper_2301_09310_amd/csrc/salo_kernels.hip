@@ -1104,6 +1104,10 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
     }
 }
 
+// Sleeps of 127 * 64 clocks (about 3.4 us) per wave slot before a
+// persistent wave's first claim.
+constexpr int kClaimStagger = 4;
+
 // Persistent mode: one launch; each wave claims units (a run of
 // near-equal pairs of one length bin, in descending cost order) from an
 // atomic counter until the planned units are exhausted.  The lane-group
@@ -1122,6 +1126,24 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
     uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
     const int lane = threadIdx.x & (kWave - 1);
     const int total = __builtin_amdgcn_readfirstlane(*P.total_units);
+    // Spread the first claims over the SIMDs.  The queue starts with the
+    // costliest units; left to arrival order, the waves dispatched first
+    // (several to a SIMD) take them, and a batch with fewer long units than
+    // SIMDs runs them stacked.  A wave that is not in its SIMD's first wave
+    // slot (HW_ID.WAVE_ID > 0) sleeps a few microseconds per slot before
+    // its first claim, and stops sleeping once every unit is claimed (a
+    // small batch then ends as soon as its work does).  Timed sleeps: no
+    // wave waits on another.
+    {
+        const int slot_id = __builtin_amdgcn_s_getreg((3 << 11) | (0 << 6) | 4) & 15;
+        const int naps = min(slot_id, 3) * kClaimStagger;
+        for (int k = 0; k < naps; ++k) {
+            __builtin_amdgcn_s_sleep(127);
+            const int claimed = __builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(P.unit_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            if (claimed >= total) break;
+        }
+    }
     for (;;) {
         int u = 0;
         if (lane == 0) u = atomicAdd(P.unit_counter, 1);
