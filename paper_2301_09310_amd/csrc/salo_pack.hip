@@ -8,13 +8,14 @@
 // Packing is a streaming pass: n bytes in, n/4 bytes out, so it is bound
 // by HBM bandwidth.
 //
-// Mapping: one thread per output 32-bit word (16 bases), 256 threads per
-// block.  Forward packing reads the word's 16 characters as four aligned
+// Mapping: 256 threads per block.  Forward packing: one thread per output
+// 32-bit word (16 bases), reading the word's 16 characters as four aligned
 // dwords.  Reverse-complement packing needs the sequence of every output
-// base: the block finds the sequence holding its first base by a binary
-// search over the offsets, stages the following offsets in LDS, and each
-// thread walks that window; the mirrored characters of a word are
-// contiguous (in reverse), so the reads stay within a few cache lines.
+// base.  A block packs 8 words per thread.  It finds the sequences of its
+// first and last bases (a 64-lane search each), stages the offsets between
+// them in LDS, and builds a table of each word's sequence there.  The
+// mirrored characters of a word are contiguous (in reverse), so the reads
+// stay within a few cache lines.
 #include "salo_internal.h"
 
 namespace salo {
@@ -208,6 +209,8 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
                                                              uint32_t *n_mask,
                                                              unsigned long long *invalid) {
     __shared__ int64_t win[kWin + 1];
+    __shared__ int32_t wseq[kRcWords * kPackThreads];   // window index per word
+    __shared__ int32_t wave_tot[kPackThreads / 64];
     __shared__ int64_t s_first, s_last;
     constexpr int64_t kSpan = (int64_t)kRcWords * kPackThreads;   // words per block
     const int64_t w0 = (int64_t)blockIdx.x * kSpan;
@@ -231,6 +234,47 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
         const int64_t idx = s0 + t;
         win[t] = idx <= n_seqs ? off[idx] : INT64_MAX;
     }
+    for (int t = threadIdx.x; t < kSpan; t += kPackThreads) wseq[t] = -1;
+    __syncthreads();
+    // wseq[x] = the largest window index j with win[j] <= 16 * (w0 + x), or
+    // -1: each j marks the first word whose start it covers, then an
+    // inclusive max-scan carries it forward
+    {
+        const int64_t P0 = w0 << 4;
+        for (int t = threadIdx.x; t < nwin; t += kPackThreads) {
+            const int64_t v = win[t];
+            if (v == INT64_MAX) continue;
+            const int64_t x = v <= P0 ? 0 : ((v - P0 + 15) >> 4);
+            if (x < kSpan) atomicMax(&wseq[(int)x], t);
+        }
+    }
+    __syncthreads();
+    {
+        // thread t scans entries [t * kRcWords, (t + 1) * kRcWords)
+        int run = -1;
+        int loc[kRcWords];
+#pragma unroll
+        for (int k = 0; k < kRcWords; ++k) {
+            run = max(run, wseq[threadIdx.x * kRcWords + k]);
+            loc[k] = run;
+        }
+        // inclusive max-scan of the threads' totals: within the wave, then
+        // across the block's waves
+        int inc = run;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int y = __shfl_up(inc, o, 64);
+            if ((threadIdx.x & 63) >= o) inc = max(inc, y);
+        }
+        if ((threadIdx.x & 63) == 63) wave_tot[threadIdx.x >> 6] = inc;
+        __syncthreads();
+        int carry = __shfl_up(inc, 1, 64);
+        if ((threadIdx.x & 63) == 0) carry = -1;
+        for (int v = 0; v < (int)(threadIdx.x >> 6); ++v) carry = max(carry, wave_tot[v]);
+#pragma unroll
+        for (int k = 0; k < kRcWords; ++k)
+            wseq[threadIdx.x * kRcWords + k] = max(loc[k], carry);
+    }
     __syncthreads();
 
     uint32_t bad = 0;
@@ -245,13 +289,7 @@ __global__ __launch_bounds__(kPackThreads) void pack_revcomp(const uint8_t *char
             // sequence of the word's first base: window index, else the table
             int64_t s;
             {
-                int a = 0, b = nwin;
-                while (a < b) {
-                    const int mid = (a + b) >> 1;
-                    if (win[mid] <= p0) a = mid + 1;
-                    else b = mid;
-                }
-                const int j = a - 1;
+                const int j = wseq[it * kPackThreads + threadIdx.x];
                 if (j >= 0 && j + 1 < nwin && p0 < win[j + 1]) s = s0 + j;
                 else s = n_seqs > 0 ? last_le(off, 0, n_seqs, p0) : -1;
             }
