@@ -87,10 +87,29 @@ def test_random_reads_with_invalid_bases(dev):
 
 
 def test_many_tiny_sequences(dev):
-    """More than 512 sequences inside one block's 4096 bases (lengths 0..3):
-    the staged offset window runs out and the kernel searches the table."""
+    """More than 1024 sequences inside one reverse-complement block's 32,768
+    bases (lengths 0..3): the staged offset window runs out and the kernel
+    searches the offsets in global memory."""
     chars, off = _random_case(2, 20000, 3)
     _check(chars, off, "tiny sequences")
+
+
+def test_block_boundaries_and_empty_runs(dev):
+    """Sequence bounds on the reverse-complement blocks' edges (multiples of
+    32,768 bases) and next to them; a run of empty sequences (several
+    sequences mark the same word in a block's table of word sequences); and
+    1,200 two-base sequences, more than one block's window of staged
+    offsets holds."""
+    rng = np.random.default_rng(17)
+    block = 32768
+    cuts = [k * block + d for k in range(1, 6) for d in (-17, -16, -1, 0, 1, 15, 16)]
+    cuts += list(rng.integers(0, 6 * block, 300))
+    cuts += [2 * block + 5] * 7
+    cuts += list(4 * block + 100 + np.arange(0, 2400, 2))
+    total = 6 * block + 123
+    off = np.concatenate([[0], np.sort(np.array(cuts, np.int64)), [total]]).astype(np.int64)
+    chars = LETTERS[rng.integers(0, 4, total)]
+    _check(chars, off, "block edges")
 
 
 def test_single_long_sequence(dev):
