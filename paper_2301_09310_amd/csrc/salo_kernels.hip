@@ -363,10 +363,10 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
         uint32_t nib;
         if constexpr (PKD) {
             const uint32_t w = *reinterpret_cast<const uint32_t *>(
-                codes + ((int64_t)(c * W + lq) * rows + i) * K + 4 * (k >> 2));
+                codes + (((int64_t)c * rows + i) * W + lq) * K + 4 * (k >> 2));
             nib = (w >> (16 * half + 4 * (3 - (k & 3)))) & 15u;
         } else {
-            const uint8_t byte = codes[((int64_t)(c * W + lq) * rows + i) * (K / 2) + (k >> 1)];
+            const uint8_t byte = codes[(((int64_t)c * rows + i) * W + lq) * (K / 2) + (k >> 1)];
             nib = (byte >> ((k & 1) * 4)) & 15u;
         }
         uint32_t op;
@@ -508,10 +508,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
     const Slot bslot{slot};
     // trace pass: this group's share of the block's code slot; the pair's
-    // codes take (its chunks) x W lanes x n rows x K/2 bytes, laid out
-    // [chunk][lane][row] so that a lane's consecutive rows are adjacent
-    // (16-bit cells: the group's two pairs share K bytes per lane and row,
-    // over the larger pair's chunks and rows)
+    // codes take (its chunks) x n rows x W lanes x K/2 bytes, laid out
+    // [chunk][row][lane] so that the group's stores of one step are
+    // adjacent and fill whole lines quickly (16-bit cells: the group's two
+    // pairs share K bytes per lane and row, over the larger pair's chunks
+    // and rows)
     uint8_t *tr_codes = nullptr;
     bool tr_fits = false;
     int tr_chunks = 0, tr_rows = 0;
@@ -645,7 +646,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         uint8_t *tr_lane = nullptr;
         if constexpr (TR) {
             if (tr_fits && mine && c < tr_chunks)
-                tr_lane = tr_codes + (int64_t)(c * W + l) * tr_rows * kTrRowBytes;
+                tr_lane = tr_codes + ((int64_t)c * tr_rows * W + l) * kTrRowBytes;
         }
         uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
         uint32_t cbest = 0;           // packed (or wide) best row maximum in this chunk
@@ -850,7 +851,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             facc[w] = fnew[w];
                         }
                         if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
-                            uint8_t *dst = tr_lane + (int64_t)i * kTrRowBytes;
+                            uint8_t *dst = tr_lane + (int64_t)i * W * kTrRowBytes;
                             if constexpr (K == 8) {
                                 *reinterpret_cast<uint2 *>(dst) = make_uint2(acc[0], acc[1]);
                             } else {
@@ -896,7 +897,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     if constexpr (TR) {
                         fbits = fnext;
                         if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
-                            uint8_t *dst = tr_lane + (int64_t)i * kTrRowBytes;
+                            uint8_t *dst = tr_lane + (int64_t)i * W * kTrRowBytes;
                             if constexpr (K == 8) {
                                 *reinterpret_cast<uint32_t *>(dst) = code[0];
                             } else if constexpr (K == 16) {
