@@ -13,8 +13,8 @@
  *     F(i,j) = max{ H(i-1,j) - alpha, F(i-1,j) - beta }
  *
  * with i indexing the reference (target) and j the query (Section II-A, the
- * sentence after Eq. 1), and the answer "the highest score in the table"
- * (Section II-A, description of the example figure).
+ * sentence after Eq. 1), and the answer is the maximum H over the whole
+ * table (Section II-A, the description of the example figure).
  *
  * Readings of points the paper leaves open (each is listed in the design
  * notes of the repository):
@@ -157,11 +157,18 @@ static void *worker(void *arg)
     return NULL;
 }
 
-static const int64_t *g_cells_for_sort;
+/* Longest-first schedule: (cells, pair) records sorted by descending cell
+ * count.  The comparator reads only its two records, so concurrent batch
+ * calls from several host threads share no state. */
+typedef struct {
+    int64_t cells;
+    int64_t pair;
+} sched_t;
+
 static int cmp_cells_desc(const void *a, const void *b)
 {
-    const int64_t x = g_cells_for_sort[*(const int64_t *)a];
-    const int64_t y = g_cells_for_sort[*(const int64_t *)b];
+    const int64_t x = ((const sched_t *)a)->cells;
+    const int64_t y = ((const sched_t *)b)->cells;
     return (x < y) - (x > y);
 }
 
@@ -195,18 +202,19 @@ int oracle_align_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
     jb.score = out_score; jb.qend = out_qend; jb.tend = out_tend;
     pthread_mutex_init(&jb.mu, NULL);
 
-    int64_t *cells = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_pairs);
+    sched_t *sched = (sched_t *)malloc(sizeof(sched_t) * (size_t)n_pairs);
     int64_t *order = (int64_t *)malloc(sizeof(int64_t) * (size_t)n_pairs);
-    if (!cells || !order) { free(cells); free(order); return -1; }
+    if (!sched || !order) { free(sched); free(order); return -1; }
     for (int64_t p = 0; p < n_pairs; ++p) {
         const int64_t m = q_offsets[p + 1] - q_offsets[p];
         const int64_t n = t_offsets[p + 1] - t_offsets[p];
-        cells[p] = m * n;
-        order[p] = p;
+        sched[p].cells = m * n;
+        sched[p].pair = p;
         if (m > jb.max_m) jb.max_m = m;
     }
-    g_cells_for_sort = cells;
-    qsort(order, (size_t)n_pairs, sizeof(int64_t), cmp_cells_desc);
+    qsort(sched, (size_t)n_pairs, sizeof(sched_t), cmp_cells_desc);
+    for (int64_t k = 0; k < n_pairs; ++k) order[k] = sched[k].pair;
+    free(sched);
     jb.order = order;
 
     int rc = 0;
@@ -227,7 +235,6 @@ int oracle_align_batch_n(const uint8_t *q_seqs, const uint32_t *q_nmask,
         }
     }
     pthread_mutex_destroy(&jb.mu);
-    free(cells);
     free(order);
     return rc;
 }
