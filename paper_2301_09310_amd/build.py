@@ -44,7 +44,10 @@ def build(jobs: int = 4, verbose: bool = True, out: str | None = None,
     if csrc:
         CSRC = csrc
     target = out or LIB
-    srcs = [s for s in SOURCES if os.path.exists(os.path.join(CSRC, s))]
+    missing = [s for s in SOURCES if not os.path.exists(os.path.join(CSRC, s))]
+    if missing:
+        raise FileNotFoundError("libsalo sources missing from %s: %s" % (CSRC, ", ".join(missing)))
+    srcs = list(SOURCES)
     tmp = tempfile.mkdtemp(prefix="salo_build_")
     try:
         objs = [os.path.join(tmp, s + ".o") for s in srcs]
