@@ -4,13 +4,20 @@
 One step = one salo_align_batch call over the whole synthetic batch (every
 pair's affine-gap Smith-Waterman-Gotoh table, Section II-A Eq. 1, plus its
 maximum and end position), inputs already resident in HBM.  Prints ONE JSON
-line.  The default workload is the short-read extension batch: 2,000,000
-pairs, query length U{50..250}, target = source + U{0..100} flank, 1%
-substitutions, 0.1% indels, 10% unrelated pairs, scoring (1, -4, 6, 1).
+line.  The default workload is the batched mixed workload: 4,000,000 pairs,
+60% of queries U{100..300}, 35% U{300..1000}, 5% U{1000..10000}, targets
+1.2x the source with the source at a random offset, 2% substitutions, 1%
+single-base indels, scoring (1, -4, 6, 1); each step (plan + persistent DP
+launches) is replayed from a HIP graph.  The line also carries the plain
+one-launch kernel on the same batch, the served stream's p50/p99 latency,
+every pair's parity against the oracle's stored digests, the roofline of
+the DP kernel against the nominal and the measured VALU peaks, and the CPU
+oracle timed on this host.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W]
-                       [--workload short_reads|plain_small|long_uneven|mixed]
+                       [--workload mixed|short_reads|plain_small|long_uneven]
                        [--mode auto|plain|persistent] [--lanes L --cols C]
+                       [--no-graph] [--no-compare-plain] [--no-serve]
                        [--no-cpu-baseline] [--parity-sample N]
 """
 from __future__ import annotations
@@ -100,26 +107,149 @@ def measured_traffic(workload: str, source_hash=None):
     return None if rec is None else float(rec["bytes_per_launch"])
 
 
+_CEILINGS = {}
+
+
+def ceilings():
+    """Measured ceilings of this GPU from the microbenchmark library
+    (libsalo_ubench.so): packed 16-bit and 32-bit VALU element-ops/s (T/s)
+    and the HBM copy rate (GB/s, bytes read + written); {} when the library
+    is missing.  Measured once per process (about a second)."""
+    if _CEILINGS or _CEILINGS.get("_done"):
+        return _CEILINGS
+    import ctypes
+    path = os.path.join(ROOT, "paper_2301_09310_amd", "libsalo_ubench.so")
+    _CEILINGS["_done"] = True
+    if not os.path.exists(path):
+        return _CEILINGS
+    lib = ctypes.CDLL(path)
+    lib.salo_ubench.argtypes = [ctypes.c_int, ctypes.c_int64, ctypes.c_int,
+                                ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]
+    lib.salo_ubench.restype = ctypes.c_int
+    for kind, key, work, reps, scale in ((0, "pk16_tops", 4000, 5, 1e12),
+                                         (1, "i32_tops", 4000, 5, 1e12),
+                                         (2, "copy_gbs", 1 << 31, 10, 1e9)):
+        ms, units = ctypes.c_double(0), ctypes.c_double(0)
+        rc = lib.salo_ubench(kind, work, reps, ctypes.byref(ms), ctypes.byref(units))
+        if rc == 0 and ms.value > 0:
+            _CEILINGS[key] = units.value / (ms.value * 1e-3) / scale
+    if "i32_tops" in _CEILINGS:
+        # one 32-bit VALU op per lane per clock: the sustained clock
+        _CEILINGS["clock_ghz"] = _CEILINGS["i32_tops"] * 1e12 / (256 * 64) / 1e9
+    log("measured ceilings: %s" % json.dumps({k: round(v, 3) for k, v in _CEILINGS.items()
+                                              if k != "_done"}))
+    return _CEILINGS
+
+
+def measured_valu_peak(dtype: str):
+    """The measured VALU peak for this cell type (element-ops/s, T/s)."""
+    c = ceilings()
+    key = "i32_tops" if dtype == "i32" else "pk16_tops"
+    return c.get(key)
+
+
+def cpu_model() -> str:
+    """The host CPU's model name (first 'model name' of /proc/cpuinfo)."""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def first_pairs_with_cells(batch, target_cells: float) -> int:
+    """Smallest prefix of pairs holding at least target_cells cells."""
+    c = np.cumsum(batch.q_lens().astype(np.int64) * batch.t_lens())
+    return int(min(batch.n_pairs, np.searchsorted(c, target_cells) + 1))
+
+
+def cpu_baseline(O, batch, workload, masks_np, all_cells: float, one_cells: float,
+                 cap_pairs: int):
+    """The oracle timed on this host: all cores on a leading sample of the
+    batch, one core on a smaller leading sample (GCUPS of each)."""
+    out = {"kind": "oracle", "unit": "GCUPS", "cpu_model": cpu_model(),
+           "nproc": os.cpu_count(), "affinity_cores": O.default_threads()}
+    for label, cells, thr in (("all_cores", all_cells, O.default_threads()),
+                              ("one_core", one_cells, 1)):
+        m = min(first_pairs_with_cells(batch, cells), cap_pairs)
+        idx = np.arange(m)
+        sub = batch.subset(idx)
+        cmq, cmt = subset_masks(batch, idx, masks_np)
+        c0 = time.perf_counter()
+        O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING,
+                      nthreads=thr, q_nmask=cmq, t_nmask=cmt)
+        dt = time.perf_counter() - c0
+        out[label] = {"gcups": round(sub.cells() / dt / 1e9, 4), "threads": thr,
+                      "pairs": m, "cells": sub.cells(), "seconds": round(dt, 2)}
+        log("cpu oracle, %s: %d pairs, %.3e cells, %.1fs, %.3f GCUPS" % (
+            label, m, sub.cells(), dt, sub.cells() / dt / 1e9))
+    a = out["all_cores"]
+    out["value"] = a["gcups"]
+    out["cores"] = a["threads"]
+    out["sample"] = ("first %d pairs of the %s batch (%.3e cells) on %d threads; one core: "
+                     "first %d pairs (%.3e cells)" % (a["pairs"], workload, a["cells"],
+                                                      a["threads"], out["one_core"]["pairs"],
+                                                      out["one_core"]["cells"]))
+    return out
+
+
+def full_parity(batch, workload, n_pairs_default, got):
+    """Digest comparison of every pair's answers with the oracle's answers
+    stored in tests/golden/full_digests.json (written by a script that runs
+    only the oracle and the generator); None when the batch has none."""
+    import hashlib
+    path = os.path.join(ROOT, "tests", "golden", "full_digests.json")
+    if not os.path.exists(path) or batch.n_pairs != n_pairs_default:
+        return None
+    with open(path) as f:
+        rec = json.load(f).get(workload)
+    if rec is None or rec.get("dataset_sha256") != batch.sha256():
+        return None
+    ok = True
+    for arr, key in zip(got, ("score", "q_end", "t_end")):
+        d = hashlib.sha256(np.ascontiguousarray(arr, dtype="<i4").tobytes()).hexdigest()
+        ok &= d == rec[key]
+    return ok
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=10)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default=None,
-                    help="default short_reads (anchored_long with --band)")
+                    help="default mixed (anchored_long with --band, short_reads with "
+                         "--trace)")
     ap.add_argument("--pairs", type=int, default=0, help="override the pair count")
     ap.add_argument("--mode", default="auto")
     ap.add_argument("--lanes", type=int, default=0)
     ap.add_argument("--cols", type=int, default=0)
     ap.add_argument("--waves-per-cu", type=int, default=0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-sample", type=int, default=2_000_000)
+    ap.add_argument("--cpu-cells", type=float, default=1.2e11,
+                    help="cells of the all-core oracle sample (leading pairs)")
+    ap.add_argument("--cpu-one-core-cells", type=float, default=4e9,
+                    help="cells of the one-core oracle sample (leading pairs)")
+    ap.add_argument("--cpu-sample", type=int, default=2_000_000,
+                    help="most pairs in either oracle sample")
     ap.add_argument("--parity-sample", type=int, default=3000)
-    ap.add_argument("--compare-plain", action="store_true")
+    ap.add_argument("--no-compare-plain", action="store_true",
+                    help="skip the plain-kernel comparison (on by default)")
+    ap.add_argument("--compare-plain", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--plain-lanes", type=int, default=64,
+                    help="lanes per group of the plain kernel (64: its best width on mixed "
+                         "lengths)")
+    ap.add_argument("--plain-steps", type=int, default=3,
+                    help="timed plain steps (a plain step on the mixed batch takes seconds)")
     ap.add_argument("--serve", action="store_true",
-                    help="served stream: Poisson arrivals of 1-4096-pair requests drawn from "
-                         "the mixed workload; prints p50/p99 latency at 0.5x/0.8x/1.2x of the "
-                         "saturated request rate")
+                    help="only the served stream: Poisson arrivals of 1-4096-pair requests "
+                         "drawn from the mixed workload; p50/p99 latency at 0.5x/0.8x/1.2x of "
+                         "the saturated request rate")
+    ap.add_argument("--no-serve", action="store_true",
+                    help="leave the served-stream block out of the mixed-workload line")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
     ap.add_argument("--serve-pool", type=int, default=1_000_000)
@@ -128,12 +258,15 @@ def main(argv=None) -> int:
                     help="launches in flight at once (one HIP stream each)")
     ap.add_argument("--serve-launch-pairs", type=int, default=1 << 17,
                     help="most pairs merged into one launch")
-    ap.add_argument("--graph", action="store_true",
-                    help="capture one step (plan + DP launches) in a HIP graph and time replays")
+    ap.add_argument("--serve-rates", default="0.5,0.8",
+                    help="offered loads as fractions of the saturated rate")
+    ap.add_argument("--graph", action="store_true", help=argparse.SUPPRESS)
+    ap.add_argument("--no-graph", action="store_true",
+                    help="time eager calls instead of replays of one captured step (plan + "
+                         "DP launches in a HIP graph, the default)")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="BYTES",
                     help="only run 3 device-to-device copies of BYTES bytes (a known-"
                          "traffic kernel for scaling the profiler's byte counters)")
-    ap.add_argument("--plain-lanes", type=int, default=4)
     ap.add_argument("--n-fraction", type=float, default=0.0,
                     help="mark this fraction of bases (both streams, seeded) as N and "
                          "align through the N-mask entry point")
@@ -149,7 +282,10 @@ def main(argv=None) -> int:
                          "characters (forward and reverse-complement)")
     args = ap.parse_args(argv)
     if args.workload is None:
-        args.workload = "anchored_long" if args.band >= 0 else "short_reads"
+        args.workload = ("anchored_long" if args.band >= 0 else
+                         "short_reads" if (args.trace or args.pack) else "mixed")
+    use_graph = not args.no_graph
+    compare_plain = not args.no_compare_plain and args.mode != "plain"
 
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -198,6 +334,7 @@ def main(argv=None) -> int:
                 log("generating %s: %d / %d pairs" % (args.workload, done, total))
         kw["progress"] = progress
     batch = gen(0, args.pairs, **kw) if args.pairs else gen(0, **kw)
+    default_pairs = gen.__defaults__[1] if gen.__defaults__ else None
     cells = batch.cells()
     log("workload %s: %d pairs, %.3e cells, generated in %.1fs" % (
         args.workload, batch.n_pairs, cells, time.time() - t0))
@@ -223,15 +360,15 @@ def main(argv=None) -> int:
                 waves_per_cu=args.waves_per_cu)
     if q_nmask is not None:
         opts.update(q_nmask=q_nmask, t_nmask=t_nmask)
-    stream = torch.cuda.current_stream()
+    stream = torch.cuda.Stream() if use_graph else torch.cuda.current_stream()
 
+    log("warm-up: %d steps" % args.warmup)
     for _ in range(args.warmup):
         salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
     torch.cuda.synchronize()
 
     graph = None
-    if args.graph:
-        stream = torch.cuda.Stream()
+    if use_graph:
         with torch.cuda.stream(stream):
             salo.reserve(n, stream=stream)
             salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
@@ -240,6 +377,7 @@ def main(argv=None) -> int:
         with torch.cuda.graph(graph, stream=stream):
             salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
         torch.cuda.synchronize()
+        log("captured one step (plan + DP launches) in a HIP graph")
 
     # timed region: K steps between events recorded on the launch stream;
     # the library also records events around its plan and DP kernels
@@ -259,53 +397,63 @@ def main(argv=None) -> int:
         plan_ms.append(a)
         dp_ms.append(b)
     ev1.record(stream)
-    if graph is not None:
-        # kernel durations of one replayed step, from a separate timed call
-        torch.cuda.synchronize()
-        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, timing=True, **opts)
-        a, b = salo.last_timing(stream)
-        plan_ms.append(a)
-        dp_ms.append(b)
     torch.cuda.synchronize()
     wall = time.perf_counter() - wall0
     total_ms = ev0.elapsed_time(ev1)
     ms_per_step = total_ms / args.steps
     gcups = cells * args.steps / (total_ms * 1e-3) / 1e9
+    log("timed %d steps: %.2f ms per step, %.1f GCUPS (wall %.3fs)" % (
+        args.steps, ms_per_step, gcups, wall))
+    if graph is not None:
+        # kernel durations of the replayed step's launches, from timed
+        # eager calls of the same step on the same stream
+        for _ in range(3):
+            salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, timing=True,
+                             **opts)
+            a, b = salo.last_timing(stream)
+            plan_ms.append(a)
+            dp_ms.append(b)
+        torch.cuda.synchronize()
     log("plan ms: %s" % " ".join("%.3f" % x for x in plan_ms))
-    log("dp ms:   %s (wall %.3fs)" % (" ".join("%.2f" % x for x in dp_ms), wall))
+    log("dp ms:   %s" % " ".join("%.2f" % x for x in dp_ms))
+
+    # every pair's answers against the oracle's stored digests
+    got_all = [x.cpu().numpy() for x in out]
+    full_ok = full_parity(batch, args.workload, default_pairs, got_all) \
+        if q_nmask is None else None
+    if full_ok is not None:
+        log("every pair vs the oracle's digests: %s" % ("bit-exact" if full_ok else "MISMATCH"))
 
     comparison = None
-    if args.compare_plain and args.mode != "plain":
+    if compare_plain:
         popts = dict(mode="plain", lanes=args.plain_lanes, cols=16,
                      waves_per_cu=args.waves_per_cu)
         if q_nmask is not None:
             popts.update(q_nmask=q_nmask, t_nmask=t_nmask)
+        pout = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(3))
         t_first = time.perf_counter()
-        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
+        salo.align_batch(q, qo, t, to, SCORING, out=pout, stream=stream, **popts)
         torch.cuda.synchronize()
-        # a plain step of many seconds reports each step (the host waits
-        # between steps, so the timed launches stay back to back only when
-        # steps are short)
-        pm_progress = time.perf_counter() - t_first > 5.0
-        log("plain warm-up step: %.1f s" % (time.perf_counter() - t_first))
+        log("plain warm-up step (lanes %d): %.2f s" % (args.plain_lanes,
+                                                      time.perf_counter() - t_first))
         e0 = torch.cuda.Event(enable_timing=True)
         e1 = torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        for k in range(args.steps):
-            salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **popts)
-            if pm_progress:
-                torch.cuda.synchronize()
-                log("plain step %d done" % k)
-        e1.record(stream)
-        torch.cuda.synchronize()
-        pm = e0.elapsed_time(e1) / args.steps
+        for k in range(args.plain_steps):
+            salo.align_batch(q, qo, t, to, SCORING, out=pout, stream=stream, **popts)
+            e1.record(stream)
+            torch.cuda.synchronize()           # a plain step takes seconds: report each
+            log("plain step %d done" % k)
+        pm = e0.elapsed_time(e1) / args.plain_steps
+        same = all(torch.equal(a, b) for a, b in zip(out, pout))
         comparison = {"plain_gcups": round(cells / (pm * 1e-3) / 1e9, 2),
                       "plain_ms_per_step": round(pm, 4), "plain_lanes": args.plain_lanes,
-                      "speedup_vs_plain": round(pm / ms_per_step, 3)}
-        log("plain lanes=%d: %.2f ms/step" % (args.plain_lanes, pm))
-        # the persistent outputs must be what the parity sample checks
-        salo.align_batch(q, qo, t, to, SCORING, out=out, stream=stream, **opts)
-        torch.cuda.synchronize()
+                      "plain_cols": 16, "plain_steps": args.plain_steps,
+                      "speedup_vs_plain": round(pm / ms_per_step, 3),
+                      "plain_answers_equal": bool(same)}
+        log("plain lanes=%d: %.2f ms/step; answers equal to the persistent ones: %s" % (
+            args.plain_lanes, pm, same))
+        del pout
 
     starts = None
     if args.starts:
@@ -347,17 +495,24 @@ def main(argv=None) -> int:
         log("start pass: %.3f ms per step (DP %.3f), %.1f GCUPS over the reversed prefixes, %s"
             % (s_ms, starts["dp_ms"], starts["gcups"], starts["parity"]))
 
-    # parity on a sample of pairs (the full-size check lives in the tests)
+    # parity on a sample of pairs, recomputed by the oracle here
     rng = np.random.default_rng(1)
     k = min(args.parity_sample, n)
     idx = np.sort(rng.choice(n, size=k, replace=False))
-    got = [x.cpu().numpy()[idx].astype(np.int64) for x in out]
+    got = [x[idx].astype(np.int64) for x in got_all]
     sub = batch.subset(idx)
     sqm, stm = subset_masks(batch, idx, masks_np)
     want = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING,
                          q_nmask=sqm, t_nmask=stm)
-    parity_ok = all(np.array_equal(g, w) for g, w in zip(got, want))
-    log("parity on %d sampled pairs: %s" % (k, "bit-exact" if parity_ok else "MISMATCH"))
+    sample_ok = all(np.array_equal(g, w) for g, w in zip(got, want))
+    log("parity on %d sampled pairs: %s" % (k, "bit-exact" if sample_ok else "MISMATCH"))
+    parity_ok = sample_ok and full_ok is not False
+    if full_ok is not None:
+        parity = ("bit-exact on all %d pairs (oracle digests) and on %d pairs recomputed by "
+                  "the oracle here" % (n, k)) if parity_ok else "MISMATCH"
+    else:
+        parity = "bit-exact on %d sampled pairs" % k if parity_ok else \
+            "MISMATCH on sampled pairs"
 
     # roofline of the DP kernel: algorithmic int ops per launch / launch time
     dtype = cell_dtype(batch, n_masks=q_nmask is not None)
@@ -370,21 +525,25 @@ def main(argv=None) -> int:
             "kernel": ("plain_kernel" if args.mode == "plain" else "persistent_kernel"),
             "kernel_ms": round(kern_ms, 4), "ops_per_cell": OPS_PER_CELL,
             "traffic_unit": "bytes per launch", "kernel_source": kernel_source_hash()}
+    measured_peak = measured_valu_peak(dtype)
+    if measured_peak is not None:
+        roof["measured_peak"] = round(measured_peak, 3)
+        roof["frac_of_measured_peak"] = round(achieved / measured_peak, 4)
+        roof["measured_ceilings"] = {k: round(v, 3) for k, v in ceilings().items()
+                                     if k != "_done"}
+    if traffic is not None:
+        roof["hbm_frac"] = round(traffic / (kern_ms * 1e-3) / 1e9 / HBM_PEAK_GBS, 5)
+
+    serve = None
+    if args.workload == "mixed" and not args.no_serve and q_nmask is None:
+        del q, qo, t, to
+        torch.cuda.empty_cache()
+        serve = serve_block(args, batch)
 
     cpu = None
     if not args.no_cpu_baseline:
-        m = min(args.cpu_sample, n)
-        sub = batch.subset(np.arange(m))
-        cmq, cmt = subset_masks(batch, np.arange(m), masks_np)
-        thr = O.default_threads()
-        c0 = time.perf_counter()
-        O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, SCORING,
-                      nthreads=thr, q_nmask=cmq, t_nmask=cmt)
-        dt = time.perf_counter() - c0
-        cpu = {"value": round(sub.cells() / dt / 1e9, 4), "unit": "GCUPS", "cores": thr,
-               "kind": "oracle",
-               "sample": "first %d pairs of the %s batch (%.3e cells), %.1fs" % (
-                   m, args.workload, sub.cells(), dt)}
+        cpu = cpu_baseline(O, batch, args.workload, masks_np, args.cpu_cells,
+                           args.cpu_one_core_cells, args.cpu_sample)
 
     rec = {
         "metric": METRIC, "value": round(gcups, 2), "unit": "GCUPS", "n_gpus": 1,
@@ -393,14 +552,14 @@ def main(argv=None) -> int:
         "dtype": dtype, "data": "synthetic",
         "config": {"workload": args.workload, "pairs": n, "cells": cells,
                    "scoring": list(SCORING), "mode": args.mode, "lanes": args.lanes,
-                   "cols": args.cols, "parity": "bit-exact on %d sampled pairs" % k
-                   if parity_ok else "MISMATCH on sampled pairs",
-                   "plan_ms": round(float(np.mean(plan_ms)), 4), "graph": bool(args.graph),
+                   "cols": args.cols, "parity": parity,
+                   "plan_ms": round(float(np.mean(plan_ms)), 4), "graph": graph is not None,
                    "n_fraction": args.n_fraction,
                    "dp_ms": round(kern_ms, 4)},
         "roofline": roof,
         "cpu_baseline": cpu,
         "comparison": comparison,
+        "serve": serve,
         "starts": starts,
     }
     print(json.dumps(rec), flush=True)
@@ -731,40 +890,48 @@ def pack_bench(args) -> int:
     return 0 if ok else 1
 
 
-def serve_bench(args) -> int:
-    """p50/p99 request latency of the served stream at fixed offered rates."""
+def serve_block(args, pool):
+    """Served stream on the GPU: Poisson arrivals of requests of U{1..4096}
+    pairs carved from consecutive pairs of `pool` (a mixed batch), served by
+    continuous batching with admission by HBM footprint.  Runs all requests
+    at once to find the saturated rate, then open-loop Poisson streams at the
+    fractions of it given by --serve-rates; returns p50/p99 latency and
+    GCUPS per rate, with the served answers of sampled requests checked
+    against the oracle."""
     from oracle import oracle as O
-    from paper_2301_09310_amd import inputs as I
     from paper_2301_09310_amd import serve as S
-    t0 = time.time()
-    pool = I.mixed(0, args.serve_pool)
-    log("serve pool: %d mixed pairs in %.1fs" % (pool.n_pairs, time.time() - t0))
     n = args.serve_warmup + args.serve_requests
     sizes = S.request_sizes(n, 1)
     budget = int(args.serve_budget_gb * (1 << 30))
+    t0 = time.time()
+    base = S.split_requests(pool, sizes, np.zeros(n))
+    log("serve: %d requests (%d pairs) carved from the %d-pair pool in %.1fs" % (
+        n, int(sizes.sum()), pool.n_pairs, time.time() - t0))
     ex = S.GpuExecutor(n_slots=args.serve_slots, max_pairs=args.serve_launch_pairs,
                        scoring=SCORING)
 
     def run(rate):
         arr = np.zeros(n) if rate is None else S.poisson_arrivals(n, rate, 1)
-        reqs = S.split_requests(pool, sizes, arr)
+        reqs = S.with_arrivals(base, arr)
         st = S.Server(ex, budget_bytes=budget, progress=log).run(reqs,
                                                                  warmup=args.serve_warmup)
         return reqs, st.summary()
 
     reqs, sat = run(None)              # all requests at once: saturated rate
-    log("saturated: %s" % json.dumps(sat))
+    log("serve saturated: %s" % json.dumps(sat))
     rate_sat = sat["requests_per_s"]
-    # parity: a sample of served requests against the oracle
     rng = np.random.default_rng(2)
     ok = True
-    for r in rng.choice(reqs[args.serve_warmup:], size=20, replace=False):
-        b = r.batch
-        want = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, SCORING)
-        ok &= all(np.array_equal(g.astype(np.int64), w) for g, w in zip(r.result, want))
+    checked = rng.choice(np.arange(args.serve_warmup, n), size=min(20, args.serve_requests),
+                         replace=False)
     runs = {}
-    for f in (0.5, 0.8, 1.2):
-        _, summ = run(f * rate_sat)
+    for f in [float(x) for x in args.serve_rates.split(",") if x]:
+        reqs, summ = run(f * rate_sat)
+        for k in checked:
+            b = reqs[k].batch
+            want = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, SCORING)
+            ok &= reqs[k].status == "done" and all(
+                np.array_equal(g.astype(np.int64), w) for g, w in zip(reqs[k].result, want))
         runs["%.1fx" % f] = {"offered_rps": round(f * rate_sat, 2),
                               "p50_ms": round(summ["p50_ms"], 3),
                               "p99_ms": round(summ["p99_ms"], 3),
@@ -773,20 +940,35 @@ def serve_bench(args) -> int:
                               "mean_requests_per_launch":
                                   round(summ["mean_requests_per_launch"], 2),
                               "max_inflight": summ["max_inflight"]}
-        log("%.1fx: %s" % (f, json.dumps(runs["%.1fx" % f])))
-    rec = {"metric": METRIC, "value": runs["0.8x"]["p99_ms"], "unit": "ms (p99 at 0.8x)",
+        log("serve %.1fx: %s" % (f, json.dumps(runs["%.1fx" % f])))
+    return {"requests": args.serve_requests, "warmup_requests": args.serve_warmup,
+            "pairs_per_request": "U{1..4096}", "arrivals": "Poisson (seed 1)",
+            "budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
+            "launch_pairs": args.serve_launch_pairs,
+            "parity": ("bit-exact on %d sampled requests at every rate" % len(checked))
+            if ok else "MISMATCH",
+            "saturated": {"requests_per_s": round(rate_sat, 2), "gcups": round(sat["gcups"], 1),
+                          "mean_requests_per_launch": round(sat["mean_requests_per_launch"], 2),
+                          "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3)},
+            "rates": runs}
+
+
+def serve_bench(args) -> int:
+    """p50/p99 request latency of the served stream at fixed offered rates
+    (its own JSON line; the default mixed-workload line carries the same
+    block)."""
+    from paper_2301_09310_amd import inputs as I
+    t0 = time.time()
+    pool = I.mixed(0, args.serve_pool)
+    log("serve pool: %d mixed pairs in %.1fs" % (pool.n_pairs, time.time() - t0))
+    blk = serve_block(args, pool)
+    p99 = blk["rates"].get("0.8x", next(iter(blk["rates"].values())))["p99_ms"]
+    rec = {"metric": METRIC, "value": p99, "unit": "ms (p99 at 0.8x)",
            "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f16x2+u16x2",
-           "config": {"workload": "served mixed requests", "requests": args.serve_requests,
-                      "warmup_requests": args.serve_warmup, "pairs_per_request": "U{1..4096}",
-                      "pool_pairs": pool.n_pairs, "budget_gb": args.serve_budget_gb,
-                      "slots": args.serve_slots, "launch_pairs": args.serve_launch_pairs,
-                      "parity": "bit-exact on 20 sampled requests" if ok else "MISMATCH"},
-           "saturated": {"requests_per_s": round(rate_sat, 2), "gcups": round(sat["gcups"], 1),
-                         "mean_requests_per_launch": round(sat["mean_requests_per_launch"], 2),
-                         "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3)},
-           "rates": runs}
+           "config": {"workload": "served mixed requests", "pool_pairs": pool.n_pairs},
+           "serve": blk}
     print(json.dumps(rec), flush=True)
-    return 0 if ok else 1
+    return 0 if blk["parity"] != "MISMATCH" else 1
 
 
 if __name__ == "__main__":

@@ -8,8 +8,7 @@
  *     E(i,j) = max{H(i,j-1) - alpha, E(i,j-1) - beta}
  *     F(i,j) = max{H(i-1,j) - alpha, F(i-1,j) - beta}
  * with i over target (reference) bases and j over query bases, and return
- * the highest cell ("the highest score in the DP table", Section II-A) and
- * its position.  Batches of pairs of uneven length are the workload of
+ * the maximum H over the table and its position (Section II-A, Eq. 1).  Batches of pairs of uneven length are the workload of
  * Section III-A (load imbalance) and Section V-D.
  *
  * Scoring (salo_scoring_t): S(i,j) = match when the bases are equal and
@@ -39,7 +38,12 @@
  * outputs and keeps them alive until `stream` has passed the call; inputs
  * are never written and the three outputs are fully overwritten.  The
  * library owns a workspace per (device, stream), grown on demand outside
- * stream capture (salo_reserve pre-sizes it).
+ * stream capture (salo_reserve pre-sizes it; a call under capture that
+ * needs a larger workspace, or the first call on a stream made under
+ * capture, returns SALO_ERR_CAPTURE and enqueues nothing).  Once a call on
+ * a stream has been captured into a graph, the buffers that graph uses are
+ * never freed before salo_release(), even when a later, larger call on the
+ * stream grows the workspace, so the graph stays valid to replay.
  *
  * Errors and synchronisation: host-checkable errors return a negative
  * status and enqueue nothing (NULL pointer with n_pairs > 0, n_pairs < 0,
@@ -108,7 +112,7 @@ typedef struct {
     int32_t m_hi;       /* 1..65535, increasing within each kind */
     int32_t packed;     /* 1: 16-bit bin, 0: 32-bit bin */
     int32_t lanes;      /* 1, 2, 4, 8, 16, 32 or 64 */
-    int32_t reserved;   /* must be 0 */
+    int32_t cols;       /* query columns per lane: 8, 16 or 32; 0 means 16 */
 } salo_bin_t;
 
 #define SALO_MAX_BINS 16
@@ -320,6 +324,36 @@ salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64
                               int64_t n_seqs, int32_t revcomp, uint8_t *packed,
                               uint32_t *n_mask, unsigned long long *invalid_count,
                               hipStream_t stream);
+
+/*
+ * salo_align_batch_ex with per-request completion, for serving several
+ * requests merged into one call: pair p belongs to request pair_tag[p]
+ * (DEVICE int32 [n_pairs]; a negative tag means no request), and as soon
+ * as pair p's three outputs are written the library adds 1 to
+ * tag_done[pair_tag[p]] with a system-scope release, so a host thread that
+ * reads tag_done[r] == (pairs of request r) can read that request's outputs
+ * while the rest of the call still runs.  tag_done must be host memory the
+ * device can update coherently (salo_host_alloc) and must hold every tag
+ * used; the caller zeroes the counters before the call.  When the output
+ * arrays are also such host memory, they need no copy back.  Arguments,
+ * options, layout and errors otherwise as salo_align_batch_ex (NULL
+ * pair_tag or tag_done with n_pairs > 0: SALO_ERR_INVALID).
+ */
+salo_status_t salo_align_batch_tagged(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                      const uint8_t *t_seqs, const int64_t *t_offsets,
+                                      int64_t n_pairs, salo_scoring_t scoring,
+                                      int32_t *out_score, int32_t *out_qend, int32_t *out_tend,
+                                      const int32_t *pair_tag, uint32_t *tag_done,
+                                      hipStream_t stream, const salo_options_t *opts);
+
+/* Pinned host memory that the host and the device both read and write
+ * coherently (hipHostMalloc with the coherent flag), for salo_align_batch_
+ * tagged's counters and outputs; *ptr is usable on the host and, as the
+ * same address, in device calls.  salo_host_free releases it (no call may
+ * still use it).  bytes <= 0 or NULL ptr: SALO_ERR_INVALID; failure:
+ * SALO_ERR_NOMEM. */
+salo_status_t salo_host_alloc(int64_t bytes, void **ptr);
+salo_status_t salo_host_free(void *ptr);
 
 /* Message for the last non-OK status returned on this host thread. */
 const char *salo_last_error(void);

@@ -1,17 +1,23 @@
-"""Autotuner of the persistent mode's lane-group width per length bin.
+"""Autotuner of the persistent mode's tile shape per length bin: the
+lane-group width W and the query columns per lane K.
 
 For every bin of the table (a query-length range, 16-bit or 32-bit cells)
 it draws a synthetic batch whose queries fall in that range (targets 1.0 to
 1.5 times the query, half of the pairs related), times the persistent
-kernel with each admissible width forced, and keeps the fastest.  The
-width is the paper's subwarp-size knob (SALoBa, Section IV-C, and its sweep
-of Section V-D): narrow groups waste less of the wavefront's ramp and of the
-last chunk, wide groups finish a long pair sooner.
+kernel with each admissible (W, K) forced, checks that every shape gives
+the same answers, and keeps the fastest.  W is the paper's subwarp-size
+knob (SALoBa, Section IV-C, and its sweep of Section V-D): narrow groups
+waste less of the wavefront's ramp, wide groups finish a long pair sooner.
+K sets the chunk width W*K with W: the padding of a pair's last chunk, how
+often the boundary column is handed over, and the registers per lane
+(K = 32 runs 2 waves per SIMD instead of 3).
 
 Usage (on the GPU):
   python -m paper_2301_09310_amd.autotune --out paper_2301_09310_amd/tune_gfx950.json
-The JSON holds the table and every measurement; salo.load_tune_table(path)
-installs it, and the library's built-in table is a copy of the last run.
+The JSON holds the table and every measurement.  The library's build
+(paper_2301_09310_amd/build.py) compiles the JSON's table in as the
+built-in default, and salo.load_tune_table(path) installs another record at
+run time.
 """
 from __future__ import annotations
 
@@ -25,6 +31,7 @@ import time
 import numpy as np
 
 WIDTHS = (1, 2, 4, 8, 16, 32, 64)
+COLS = (8, 16, 32)
 ROWS_PER_LANE = 1024     # a width-W bin admits targets of up to 1024*W bases
 
 
@@ -70,7 +77,7 @@ def time_config(dev_batch, n, reps=3, **opts):
     return float(np.median(ms)), out
 
 
-def tune(cells_per_bin: float = 2e10, cols: int = 16, seed: int = 7, log=print):
+def tune(cells_per_bin: float = 2e10, cols=COLS, seed: int = 7, log=print):
     import torch
     from paper_2301_09310_amd import salo
     cus = torch.cuda.get_device_properties(0).multi_processor_count
@@ -79,7 +86,7 @@ def tune(cells_per_bin: float = 2e10, cols: int = 16, seed: int = 7, log=print):
     table = salo.get_bins()
     prev = {0: 0, 1: 0}
     result = []
-    for m_hi, packed, default_w in table:
+    for m_hi, packed, _w, _k in table:
         m_lo = prev[packed]
         prev[packed] = m_hi
         b = bin_batch(m_lo, m_hi, cells_per_bin, seed, min_pairs=min_pairs)
@@ -87,24 +94,27 @@ def tune(cells_per_bin: float = 2e10, cols: int = 16, seed: int = 7, log=print):
         dev = salo.to_device(b)
         timings = {}
         ref = None
-        for w in WIDTHS:
-            if n_max > ROWS_PER_LANE * w:
-                continue
-            ms, out = time_config(dev, b.n_pairs, mode="persistent", lanes=w, cols=cols,
-                                  force_int32=not packed)
-            res = tuple(x.cpu() for x in out)
-            if ref is None:
-                ref = res
-            elif not all(torch.equal(x, y) for x, y in zip(res, ref)):
-                raise RuntimeError("width %d changed the results of bin %d" % (w, m_hi))
-            timings[w] = ms
+        for k in cols:
+            for w in WIDTHS:
+                if n_max > ROWS_PER_LANE * w:
+                    continue
+                ms, out = time_config(dev, b.n_pairs, mode="persistent", lanes=w, cols=k,
+                                      force_int32=not packed)
+                res = tuple(x.cpu() for x in out)
+                if ref is None:
+                    ref = res
+                elif not all(torch.equal(x, y) for x, y in zip(res, ref)):
+                    raise RuntimeError("lanes %d cols %d changed the results of bin %d"
+                                       % (w, k, m_hi))
+                timings[(w, k)] = ms
         best = min(timings, key=timings.get)
         gcups = b.cells() / (timings[best] * 1e-3) / 1e9
-        log("bin m<=%5d %s: %d pairs %.2e cells; best lanes %d (%.0f GCUPS); %s" % (
-            m_hi, "16-bit" if packed else "32-bit", b.n_pairs, b.cells(), best, gcups,
-            " ".join("%d:%.2fms" % (w, t) for w, t in timings.items())))
-        result.append({"m_hi": m_hi, "packed": packed, "lanes": best, "pairs": b.n_pairs,
-                       "cells": b.cells(), "ms": {str(w): round(t, 4) for w, t in timings.items()}})
+        log("bin m<=%5d %s: %d pairs %.2e cells; best lanes %d cols %d (%.0f GCUPS); %s" % (
+            m_hi, "16-bit" if packed else "32-bit", b.n_pairs, b.cells(), best[0], best[1],
+            gcups, " ".join("%dx%d:%.2fms" % (w, k, t) for (w, k), t in timings.items())))
+        result.append({"m_hi": m_hi, "packed": packed, "lanes": best[0], "cols": best[1],
+                       "pairs": b.n_pairs, "cells": b.cells(),
+                       "ms": {"%dx%d" % wk: round(t, 4) for wk, t in timings.items()}})
     return result
 
 
@@ -112,16 +122,17 @@ def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tune_gfx950.json"))
     ap.add_argument("--cells-per-bin", type=float, default=2e10)
-    ap.add_argument("--cols", type=int, default=16)
+    ap.add_argument("--cols", default="8,16,32", help="column counts to try")
     args = ap.parse_args(argv)
+    cols = tuple(int(x) for x in args.cols.split(","))
     import torch
     from paper_2301_09310_amd import salo
     salo.load()
     t0 = time.time()
-    bins = tune(args.cells_per_bin, args.cols, log=lambda *a: print(*a, flush=True))
+    bins = tune(args.cells_per_bin, cols, log=lambda *a: print(*a, flush=True))
     props = torch.cuda.get_device_properties(0)
     rec = {"arch": getattr(props, "gcnArchName", "gfx950"), "device": props.name,
-           "cus": props.multi_processor_count, "cols": args.cols,
+           "cus": props.multi_processor_count, "cols_tried": list(cols),
            "date": datetime.date.today().isoformat(), "seconds": round(time.time() - t0, 1),
            "bins": bins}
     with open(args.out, "w") as f:

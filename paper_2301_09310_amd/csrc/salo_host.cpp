@@ -1,6 +1,7 @@
 // Host side of the C ABI declared in include/salo.h: argument validation,
 // per-(device, stream) workspaces and kernel launches.  Every step of the
 // alignment itself runs in the gfx950 kernels (salo_kernels.hip).
+#include <algorithm>
 #include <mutex>
 #include <map>
 #include <vector>
@@ -30,11 +31,12 @@ salo_status_t hip_fail(hipError_t e, const char *what) {
 struct Workspace {
     int device = -1;
     int cus = 0;
-    uint32_t *slab = nullptr;           // kSlotBytes per slot
+    uint32_t *slab = nullptr;           // slot_words 32-bit words per slot
     int64_t slots = 0;
+    int32_t slot_words = (int32_t)kSlotWords;
     unsigned long long *errors = nullptr;
     BinDesc *bins = nullptr;
-    int32_t *counters = nullptr;        // [0] unit counter, [1] total units
+    int32_t *counters = nullptr;        // kCounterWords: unit counters and totals per class
     // plan buffers of the persistent mode
     int64_t plan_cap = 0;               // pairs the plan buffers hold
     uint16_t *keys = nullptr;
@@ -46,33 +48,17 @@ struct Workspace {
     hipEvent_t ev[3] = {nullptr, nullptr, nullptr};
     bool timed = false;
     bool timed_plan = false;
+    // a call on this stream ran under stream capture: a graph may hold the
+    // buffers' addresses, so growth keeps the old buffers (retired, freed
+    // by salo_release) instead of freeing them
+    bool captured = false;
+    // carved from caller-provided device memory: never grows or frees
+    bool external = false;
+    std::vector<void *> retired;
 };
 
 std::mutex g_mu;
 std::map<std::pair<int, hipStream_t>, Workspace> g_ws;
-
-salo_status_t get_workspace(hipStream_t stream, Workspace **out) {
-    int dev = 0;
-    hipError_t e = hipGetDevice(&dev);
-    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    std::lock_guard<std::mutex> lk(g_mu);
-    Workspace &ws = g_ws[{dev, stream}];
-    if (ws.device < 0) {
-        ws.device = dev;
-        e = hipDeviceGetAttribute(&ws.cus, hipDeviceAttributeMultiprocessorCount, dev);
-        if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
-        e = hipMalloc(&ws.errors, sizeof(unsigned long long));
-        if (e != hipSuccess) return fail(SALO_ERR_NOMEM, "workspace: error counter");
-        e = hipMemset(ws.errors, 0, sizeof(unsigned long long));
-        if (e != hipSuccess) return hip_fail(e, "hipMemset");
-        e = hipMalloc(&ws.bins, sizeof(BinDesc) * kMaxBins);
-        if (e != hipSuccess) return fail(SALO_ERR_NOMEM, "workspace: bins");
-        e = hipMalloc(&ws.counters, sizeof(int32_t) * 4);
-        if (e != hipSuccess) return fail(SALO_ERR_NOMEM, "workspace: counters");
-    }
-    *out = &ws;
-    return SALO_OK;
-}
 
 bool capturing(hipStream_t stream) {
     hipStreamCaptureStatus st = hipStreamCaptureStatusNone;
@@ -80,69 +66,146 @@ bool capturing(hipStream_t stream) {
     return st != hipStreamCaptureStatusNone;
 }
 
+// The (device, stream) workspace, created on first use.  Creation
+// allocates the error counter, bin table and counters; it is recorded only
+// once every allocation has succeeded (a failure frees what was made and
+// leaves no entry).  It cannot happen under stream capture.
+salo_status_t get_workspace(hipStream_t stream, Workspace **out) {
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_mu);
+    auto it = g_ws.find({dev, stream});
+    if (it != g_ws.end()) {
+        *out = &it->second;
+        return SALO_OK;
+    }
+    if (capturing(stream))
+        return fail(SALO_ERR_CAPTURE, "no workspace for this stream yet; call salo_reserve "
+                                      "before capturing");
+    Workspace w;
+    w.device = dev;
+    auto undo = [&](salo_status_t st, const std::string &msg) {
+        if (w.errors) (void)hipFree(w.errors);
+        if (w.bins) (void)hipFree(w.bins);
+        if (w.counters) (void)hipFree(w.counters);
+        return fail(st, msg);
+    };
+    e = hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return undo(SALO_ERR_HIP, "hipDeviceGetAttribute");
+    if (hipMalloc(&w.errors, sizeof(unsigned long long)) != hipSuccess) {
+        w.errors = nullptr;
+        return undo(SALO_ERR_NOMEM, "workspace: error counter");
+    }
+    if (hipMalloc(&w.bins, sizeof(BinDesc) * kMaxBins) != hipSuccess) {
+        w.bins = nullptr;
+        return undo(SALO_ERR_NOMEM, "workspace: bins");
+    }
+    if (hipMalloc(&w.counters, sizeof(int32_t) * kCounterWords) != hipSuccess) {
+        w.counters = nullptr;
+        return undo(SALO_ERR_NOMEM, "workspace: counters");
+    }
+    if ((e = hipMemset(w.errors, 0, sizeof(unsigned long long))) != hipSuccess)
+        return undo(SALO_ERR_HIP, std::string("hipMemset: ") + hipGetErrorString(e));
+    auto res = g_ws.emplace(std::make_pair(dev, stream), std::move(w));
+    *out = &res.first->second;
+    return SALO_OK;
+}
+
+// Free a buffer the workspace no longer uses, or keep it until
+// salo_release when a captured graph may still use it.
+void drop_buffer(Workspace &ws, void *p) {
+    if (!p) return;
+    if (ws.captured)
+        ws.retired.push_back(p);
+    else
+        (void)hipFree(p);
+}
+
+salo_status_t grow_check(const Workspace &ws, hipStream_t stream, const char *what) {
+    if (ws.external)
+        return fail(SALO_ERR_INVALID, std::string(what) + " exceeds the fixed scratch");
+    if (capturing(stream))
+        return fail(SALO_ERR_CAPTURE, std::string(what) + " must grow during stream capture; "
+                                                          "call salo_reserve first");
+    return SALO_OK;
+}
+
 salo_status_t ensure_slots(Workspace &ws, int64_t slots, hipStream_t stream) {
     if (ws.slots >= slots) return SALO_OK;
-    if (capturing(stream))
-        return fail(SALO_ERR_CAPTURE, "workspace must grow during stream capture; "
-                                      "call salo_reserve first");
+    salo_status_t st = grow_check(ws, stream, "boundary slab");
+    if (st != SALO_OK) return st;
+    uint32_t *slab = nullptr;
+    if (hipMalloc(&slab, (size_t)slots * (size_t)ws.slot_words * 4) != hipSuccess)
+        return fail(SALO_ERR_NOMEM, "workspace: boundary slab of " +
+                                        std::to_string(slots * ws.slot_words * 4) + " bytes");
     if (ws.slab) {
         hipError_t e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        (void)hipFree(ws.slab);
-        ws.slab = nullptr;
-        ws.slots = 0;
+        if (e != hipSuccess) {
+            (void)hipFree(slab);
+            return hip_fail(e, "hipStreamSynchronize");
+        }
+        drop_buffer(ws, ws.slab);
     }
-    hipError_t e = hipMalloc(&ws.slab, (size_t)slots * kSlotBytes);
-    if (e != hipSuccess) {
-        ws.slab = nullptr;
-        return fail(SALO_ERR_NOMEM, "workspace: boundary slab of " +
-                                        std::to_string(slots * kSlotBytes) + " bytes");
-    }
+    ws.slab = slab;
     ws.slots = slots;
     return SALO_OK;
 }
 
 salo_status_t ensure_plan(Workspace &ws, int64_t n_pairs, hipStream_t stream) {
     if (ws.plan_cap >= n_pairs && ws.hist) return SALO_OK;
-    if (capturing(stream))
-        return fail(SALO_ERR_CAPTURE, "plan buffers must grow during stream capture; "
-                                      "call salo_reserve first");
-    if (ws.keys || ws.hist) {
-        hipError_t e = hipStreamSynchronize(stream);
-        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
-        (void)hipFree(ws.keys);
-        (void)hipFree(ws.order);
-        ws.keys = nullptr;
-        ws.order = nullptr;
-    }
+    salo_status_t st = grow_check(ws, stream, "plan buffers");
+    if (st != SALO_OK) return st;
     const int64_t cap = n_pairs < 1024 ? 1024 : n_pairs;
-    if (hipMalloc(&ws.keys, sizeof(uint16_t) * cap) != hipSuccess ||
-        hipMalloc(&ws.order, sizeof(int32_t) * cap) != hipSuccess) {
-        ws.plan_cap = 0;
+    uint16_t *keys = nullptr;
+    int32_t *order = nullptr;
+    uint32_t *hist = nullptr, *block_sums = nullptr;
+    int32_t *binstat = nullptr;
+    bool ok = hipMalloc(&keys, sizeof(uint16_t) * cap) == hipSuccess &&
+              hipMalloc(&order, sizeof(int32_t) * cap) == hipSuccess;
+    if (ok && !ws.hist)
+        ok = hipMalloc(&hist, sizeof(uint32_t) * kHistEntries) == hipSuccess &&
+             hipMalloc(&block_sums, sizeof(uint32_t) * kScanBlocks) == hipSuccess &&
+             hipMalloc(&binstat, sizeof(int32_t) * 3 * kMaxBins) == hipSuccess;
+    if (!ok) {
+        for (void *q : {(void *)keys, (void *)order, (void *)hist, (void *)block_sums,
+                        (void *)binstat})
+            if (q) (void)hipFree(q);
         return fail(SALO_ERR_NOMEM, "workspace: plan buffers");
     }
+    if (ws.keys || ws.order) {
+        hipError_t e = hipStreamSynchronize(stream);
+        if (e != hipSuccess) {
+            for (void *q : {(void *)keys, (void *)order, (void *)hist, (void *)block_sums,
+                            (void *)binstat})
+                if (q) (void)hipFree(q);
+            return hip_fail(e, "hipStreamSynchronize");
+        }
+        drop_buffer(ws, ws.keys);
+        drop_buffer(ws, ws.order);
+    }
+    ws.keys = keys;
+    ws.order = order;
     if (!ws.hist) {
-        if (hipMalloc(&ws.hist, sizeof(uint32_t) * kHistEntries) != hipSuccess ||
-            hipMalloc(&ws.block_sums, sizeof(uint32_t) * kScanBlocks) != hipSuccess ||
-            hipMalloc(&ws.binstat, sizeof(int32_t) * 3 * kMaxBins) != hipSuccess)
-            return fail(SALO_ERR_NOMEM, "workspace: plan histogram");
+        ws.hist = hist;
+        ws.block_sums = block_sums;
+        ws.binstat = binstat;
     }
     ws.plan_cap = cap;
     return SALO_OK;
 }
 
-// Length bins of the persistent mode: (m_hi, packed, lanes).  Query-length
-// ranges double from bin to bin; the built-in widths come from the
-// autotuner's sweep on one MI355X and can be replaced with salo_set_bins.
-const salo_bin_t kDefaultBins[] = {
-    {64, 1, 2, 0},    {128, 1, 2, 0},   {256, 1, 4, 0},   {512, 1, 8, 0},
-    {1024, 1, 64, 0}, {2048, 1, 32, 0}, {4096, 1, 64, 0}, {65535, 1, 64, 0},
-    {1024, 0, 32, 0}, {65535, 0, 64, 0},
-};
+// Length bins of the persistent mode: (m_hi, packed, lanes, cols).  Query-
+// length ranges double from bin to bin; the built-in table is the
+// autotuner's record for one MI355X (tune_gfx950.json), turned into
+// kDefaultBins by the build, and can be replaced with salo_set_bins.
+#include "salo_tune_table.inc"
 
 std::mutex g_bins_mu;
 std::vector<salo_bin_t> g_bins(std::begin(kDefaultBins), std::end(kDefaultBins));
 
+// cols: forced query columns per lane for every bin, or 0 for each bin's
+// own (its table entry; 0 there means 16).
 BinTable make_bin_table(int cols, int forced_lanes) {
     std::lock_guard<std::mutex> lk(g_bins_mu);
     BinTable bt;
@@ -156,7 +219,7 @@ BinTable make_bin_table(int cols, int forced_lanes) {
         prev_hi[e.packed] = e.m_hi;
         bt.packed[b] = e.packed;
         bt.lanes[b] = forced_lanes ? forced_lanes : e.lanes;
-        bt.cols[b] = cols;
+        bt.cols[b] = cols ? cols : (e.cols ? e.cols : 16);
     }
     return bt;
 }
@@ -198,6 +261,11 @@ struct StartArgs {
 };
 struct NMasks {
     const uint32_t *q, *t;   // either may be nullptr
+};
+// Per-request completion of the forward pass (salo_align_batch_tagged).
+struct Signal {
+    const int32_t *tag;
+    uint32_t *done;
 };
 // Trace pass: the answers' starts, the CIGAR buffers and the code workspace.
 struct TraceArgs {
@@ -261,7 +329,8 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
                         salo_scoring_t scoring, int32_t *out_score, int32_t *out_qend,
                         int32_t *out_tend, hipStream_t stream, const salo_options_t *opts,
                         const StartArgs *starts, NMasks masks, int32_t band = -1,
-                        const TraceArgs *trace = nullptr) {
+                        const TraceArgs *trace = nullptr, Workspace *ext = nullptr,
+                        Signal sig = Signal{nullptr, nullptr}) {
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
@@ -281,9 +350,13 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
         return fail(SALO_ERR_UNSUPPORTED, "the trace pass supports cols 8 or 16");
     if (n_pairs == 0) return SALO_OK;
 
-    Workspace *ws = nullptr;
-    salo_status_t st = get_workspace(stream, &ws);
-    if (st != SALO_OK) return st;
+    Workspace *ws = ext;
+    salo_status_t st = SALO_OK;
+    if (!ws) {
+        st = get_workspace(stream, &ws);
+        if (st != SALO_OK) return st;
+        if (capturing(stream)) ws->captured = true;
+    }
 
     // resident waves per CU at the kernel's register budget: 3 per SIMD for
     // 8 or 16 query columns per lane, 2 per SIMD for 32
@@ -292,11 +365,18 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     // most 160 (measured: the narrower chunks it allows waste fewer cells)
     // (the trace pass: 16 columns, at 2 waves per SIMD, measured faster
     // than 8 at 3: 41.6 vs 51.6 ms for its fill on short reads)
-    const int cols_default = (band >= 0 && band <= 160) ? 8 : 16;
-    const int cols_req = o.cols ? o.cols : cols_default;
-    const int wpc = o.waves_per_cu ? o.waves_per_cu
-                                   : (cols_req >= 32 || (trace && cols_req > 8) ? 8 : 12);
-    const int64_t grid = (int64_t)ws->cus * wpc;
+    // (the default pass: each length bin's own column count, one persistent
+    // launch per column class, 12 resident waves per CU for 8 or 16
+    // columns, 8 for 32)
+    const int cols_forced = o.cols ? o.cols
+                                   : (band >= 0 ? (band <= 160 ? 8 : 16) : (trace ? 16 : 0));
+    auto wpc_of = [&](int cols) {
+        return o.waves_per_cu ? o.waves_per_cu : (cols >= 32 || (trace && cols > 8) ? 8 : 12);
+    };
+    const int one_cols = o.mode == SALO_MODE_PLAIN ? (o.cols ? o.cols : 16) : cols_forced;
+    int64_t grid = (int64_t)ws->cus * (one_cols ? wpc_of(one_cols)
+                                                : (o.waves_per_cu ? o.waves_per_cu : 12));
+    if (ws->external && grid > ws->slots) grid = ws->slots;   // the fixed scratch's slots
     st = ensure_slots(*ws, grid, stream);
     if (st != SALO_OK) return st;
 
@@ -312,11 +392,18 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     }
     p.order = nullptr;
     p.scratch = ws->slab;
+    p.slot_words = ws->slot_words;
+    // one pair group's column must fit a slot (banded units keep a ring of
+    // rows, never more than the slot holds at this size)
+    p.max_rows = band >= 0 ? (int32_t)SALO_MAX_LEN
+                           : (int32_t)std::min<int64_t>(SALO_MAX_LEN, ws->slot_words / 2);
     p.errors = ws->errors;
     p.force_int32 = o.force_int32 ? 1 : 0;
     p.packed_ok = scoring_packed_ok(scoring.match, scoring.mismatch) ? 1 : 0;
     p.q_nmask = masks.q;
     p.t_nmask = masks.t;
+    p.pair_tag = sig.tag;
+    p.tag_done = sig.done;
     p.band = band;
     if (trace) {
         const int64_t slot = (trace->ws_bytes / grid) & ~(int64_t)255;
@@ -337,8 +424,10 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
                                                     scoring.gap_open, scoring.gap_extend);
     p.bins = ws->bins;
     p.unit_counter = ws->counters;
-    p.total_units = ws->counters + 1;
+    p.total_units = ws->counters + kColClasses;
 
+    if (o.timing && ws->external)
+        return fail(SALO_ERR_INVALID, "timing is not available on the fixed scratch");
     if (o.timing) {
         for (auto &ev : ws->ev)
             if (!ev && hipEventCreate(&ev) != hipSuccess)
@@ -368,8 +457,8 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     }
 
     // persistent, length-binned
-    const int cols = cols_req;
-    if (cols != 8 && cols != 16 && cols != 32)
+    const int cols = cols_forced;
+    if (cols != 0 && cols != 8 && cols != 16 && cols != 32)
         return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports cols 8, 16 or 32");
     if (o.lanes && !persistent_lanes_supported(o.lanes))
         return fail(SALO_ERR_UNSUPPORTED, "persistent mode supports lanes 2..64");
@@ -386,12 +475,20 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     if (e != hipSuccess) return hip_fail(e, "launch plan kernels");
     p.order = ws->order;
     if ((st = mark(1)) != SALO_OK) return st;
-    e = launch_persistent(p, cols, (int)grid, stream);
-    if (e != hipSuccess) return hip_fail(e, "launch persistent kernel");
+    // one launch per column class that a bin uses, widest first
+    bool used[kColClasses] = {false, false, false};
+    for (int b = 0; b < bt.n_bins; ++b) used[col_class(bt.cols[b])] = true;
+    for (int k : {32, 16, 8}) {
+        if (!used[col_class(k)]) continue;
+        const int64_t g = std::min<int64_t>(grid, (int64_t)ws->cus * wpc_of(k));
+        e = launch_persistent(p, k, (int)g, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch persistent kernel");
+    }
     return mark(2);
 }
 
 }  // namespace
+
 }  // namespace salo
 
 using namespace salo;
@@ -492,6 +589,42 @@ salo_status_t salo_align_trace(const uint8_t *q_seqs, const int64_t *q_offsets,
                      nullptr, stream, opts, &sa, NMasks{nullptr, nullptr}, -1, &ta);
 }
 
+salo_status_t salo_align_batch_tagged(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                      const uint8_t *t_seqs, const int64_t *t_offsets,
+                                      int64_t n_pairs, salo_scoring_t scoring,
+                                      int32_t *out_score, int32_t *out_qend, int32_t *out_tend,
+                                      const int32_t *pair_tag, uint32_t *tag_done,
+                                      hipStream_t stream, const salo_options_t *opts) {
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                out_score, out_qend, out_tend);
+    if (st != SALO_OK) return st;
+    if (n_pairs > 0 && (!pair_tag || !tag_done))
+        return fail(SALO_ERR_INVALID, "NULL pair_tag or tag_done");
+    if ((reinterpret_cast<uintptr_t>(pair_tag) | reinterpret_cast<uintptr_t>(tag_done)) & 3)
+        return fail(SALO_ERR_INVALID, "pair_tag and tag_done must be 4-byte aligned");
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
+                     out_qend, out_tend, stream, opts, nullptr, NMasks{nullptr, nullptr}, -1,
+                     nullptr, nullptr, Signal{pair_tag, tag_done});
+}
+
+salo_status_t salo_host_alloc(int64_t bytes, void **ptr) {
+    if (!ptr || bytes <= 0) return fail(SALO_ERR_INVALID, "bytes <= 0 or NULL ptr");
+    *ptr = nullptr;
+    const hipError_t e = hipHostMalloc(ptr, (size_t)bytes, hipHostMallocCoherent);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        return fail(SALO_ERR_NOMEM, std::string("hipHostMalloc: ") + hipGetErrorString(e));
+    }
+    return SALO_OK;
+}
+
+salo_status_t salo_host_free(void *ptr) {
+    if (!ptr) return SALO_OK;
+    const hipError_t e = hipHostFree(ptr);
+    if (e != hipSuccess) return hip_fail(e, "hipHostFree");
+    return SALO_OK;
+}
+
 salo_status_t salo_align_batch(const uint8_t *q_seqs, const int64_t *q_offsets,
                                const uint8_t *t_seqs, const int64_t *t_offsets,
                                int64_t n_pairs, salo_scoring_t scoring, int32_t *out_score,
@@ -558,8 +691,9 @@ salo_status_t salo_set_bins(const salo_bin_t *bins, int32_t n_bins) {
     int have[2] = {0, 0};
     for (int b = 0; b < n_bins; ++b) {
         const salo_bin_t &e = bins[b];
-        if ((e.packed != 0 && e.packed != 1) || e.reserved != 0 || !lanes_ok(e.lanes))
-            return fail(SALO_ERR_INVALID, "bin " + std::to_string(b) + ": bad packed/lanes");
+        if ((e.packed != 0 && e.packed != 1) || !lanes_ok(e.lanes) ||
+            (e.cols != 0 && e.cols != 8 && e.cols != 16 && e.cols != 32))
+            return fail(SALO_ERR_INVALID, "bin " + std::to_string(b) + ": bad packed/lanes/cols");
         if (e.m_hi <= prev[e.packed] || e.m_hi > SALO_MAX_LEN)
             return fail(SALO_ERR_INVALID, "bin " + std::to_string(b) +
                                               ": m_hi must increase within its kind");
@@ -592,15 +726,11 @@ void salo_release(void) {
         (void)hipGetDevice(&cur);
         (void)hipSetDevice(ws.device);
         (void)hipDeviceSynchronize();
-        (void)hipFree(ws.slab);
-        (void)hipFree(ws.errors);
-        (void)hipFree(ws.bins);
-        (void)hipFree(ws.counters);
-        (void)hipFree(ws.keys);
-        (void)hipFree(ws.order);
-        (void)hipFree(ws.hist);
-        (void)hipFree(ws.block_sums);
-        (void)hipFree(ws.binstat);
+        for (void *q : {(void *)ws.slab, (void *)ws.errors, (void *)ws.bins,
+                        (void *)ws.counters, (void *)ws.keys, (void *)ws.order, (void *)ws.hist,
+                        (void *)ws.block_sums, (void *)ws.binstat})
+            if (q) (void)hipFree(q);
+        for (void *q : ws.retired) (void)hipFree(q);
         for (auto ev : ws.ev)
             if (ev) (void)hipEventDestroy(ev);
         (void)hipSetDevice(cur);

@@ -3,6 +3,7 @@
 #pragma once
 #include <stdint.h>
 #include <hip/hip_runtime.h>
+#include "salo.h"
 
 namespace salo {
 
@@ -30,6 +31,15 @@ struct BinDesc {
     int32_t unit0;        // first global unit index      (device-written)
     int32_t n_min, n_max; // target length range          (device-written)
 };
+
+// Query columns per lane (K) of a bin select one of three kernel
+// instantiations; units are numbered within each such column class, and one
+// persistent launch per class claims that class's units.
+constexpr int kColClasses = 3;
+__host__ __device__ inline int col_class(int cols) { return cols == 8 ? 0 : cols == 16 ? 1 : 2; }
+// unit counters [0, kColClasses), unit totals [kColClasses, 2 kColClasses),
+// then two spare words (the fixed scratch's error counter)
+constexpr int kCounterWords = 8;
 
 // Static description of the bins, passed by value to the plan kernels.
 struct BinTable {
@@ -65,7 +75,11 @@ struct KParams {
     int32_t *out_qend;
     int32_t *out_tend;
     const int32_t *order;          // processing order of pair ids (nullptr: identity)
-    uint32_t *scratch;             // kSlotWords words per slot, one slot per block
+    uint32_t *scratch;             // slot_words words per slot, one slot per block
+    int32_t slot_words;            // boundary-slot size (kSlotWords unless the caller's
+                                   // scratch is smaller)
+    int32_t max_rows;              // longest column (target rows) a slot holds for one
+                                   // pair group; longer pairs are flagged invalid
     unsigned long long *errors;    // invalid-pair counter
     // start-position pass: the forward answers (score, q_end, t_end) of each
     // pair; the pass aligns the reversed prefixes ending there and writes
@@ -91,14 +105,21 @@ struct KParams {
     const int64_t *cig_off;
     uint32_t *cig;
     int32_t *cig_len;
+    // per-request completion (forward pass): after pair p's outputs are
+    // written, tag_done[pair_tag[p]] is incremented with a system-scope
+    // release (nullptr pair_tag: no signal; a negative tag: none for p)
+    const int32_t *pair_tag;
+    uint32_t *tag_done;
     int32_t force_int32;
     int32_t packed_ok;             // scoring admits 16-bit packed cells
     int32_t half_ok;               // scoring admits binary16 cells (and no_f16 is off)
     // persistent mode
     BinDesc *bins;                 // kMaxBins entries (device)
     int32_t n_bins;
-    int32_t *unit_counter;         // atomic work counter
-    int32_t *total_units;          // device-written
+    // per column class (kColClasses: 8, 16, 32 query columns per lane):
+    // the atomic work counter and the unit count of that class's bins
+    int32_t *unit_counter;         // [kColClasses]
+    int32_t *total_units;          // [kColClasses], device-written
 };
 
 // Scoring admits the packed 16-bit path (match + |mismatch| fits a byte).

@@ -141,29 +141,86 @@ struct BaseStream {
 };
 
 typedef unsigned int u32x2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 // The wave's boundary-column slot behind a range-checked buffer descriptor
-// of kSlotBytes: a byte offset at or past the end reads 0 and drops the
-// store (the hardware checks the offset against the descriptor's size).
-// Entries are 8 bytes, (H, E), at byte offset 8 * (row * groups + group).
+// of `bytes`: a byte offset at or past the end reads 0 and drops the store
+// (the hardware checks the offset against the descriptor's size).  Entries
+// are 8 bytes, (H, E), at byte offset 8 * (row * groups + group).
 struct Slot {
     uint32_t *base;   // wave-uniform
+    uint32_t bytes;   // wave-uniform
 
     __device__ __forceinline__ uint2 load(uint32_t off) const {
         const __amdgpu_buffer_rsrc_t r =
-            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)kSlotBytes, kBufDword3);
+            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, kBufDword3);
         const u32x2 v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)off, 0, 0);
         return make_uint2(v.x, v.y);
     }
     __device__ __forceinline__ void store(uint32_t off, uint32_t h, uint32_t e) const {
         const __amdgpu_buffer_rsrc_t r =
-            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)kSlotBytes, kBufDword3);
+            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, kBufDword3);
         u32x2 v;
         v.x = h;
         v.y = e;
         __builtin_amdgcn_raw_buffer_store_b64(v, r, (int)off, 0, 0);
     }
+    // 16 bytes per lane: one burst of the LDS ring (64 lanes x 16 B = 1 KiB)
+    __device__ __forceinline__ uint4 load16(uint32_t off) const {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, kBufDword3);
+        const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(r, (int)off, 0, 0);
+        return make_uint4(v.x, v.y, v.z, v.w);
+    }
+    __device__ __forceinline__ void store16(uint32_t off, uint4 v) const {
+        const __amdgpu_buffer_rsrc_t r =
+            __builtin_amdgcn_make_buffer_rsrc(base, 0, (int)bytes, kBufDword3);
+        u32x4 w;
+        w.x = v.x;
+        w.y = v.y;
+        w.z = v.z;
+        w.w = v.w;
+        __builtin_amdgcn_raw_buffer_store_b128(w, r, (int)off, 0, 0);
+    }
 };
+
+// The chunk-boundary column in LDS (the role of the paper's lazy spill,
+// Section IV-B, designed for one wave64 and its LDS).  A pair group's
+// column holds (H, E) of the chunk's last query column for every target
+// row, 8 bytes per row, laid out [row][group] as in the global slot.
+//  * Resident: a unit whose whole column fits kBndLdsBytes keeps it in LDS;
+//    the next chunk reads each row before this chunk overwrites it (the
+//    read of row r leads its write by W steps), so one buffer serves both.
+//  * Ring: otherwise the column lives in the wave's global slot and LDS
+//    holds two rings of two 1 KiB blocks (a block is 128 / Gs rows of all
+//    Gs groups).  The writer side stores each row into the write ring and,
+//    when a block is complete, the whole wave copies it to the slot as one
+//    coalesced 16-byte-per-lane burst.  The reader side keeps the next block
+//    in flight in four registers per lane and moves it into the read ring
+//    one block ahead of use.  So the slot sees 2 bursts per block instead of
+//    a load and a store per row, and each row is read from LDS.
+constexpr uint32_t kBndLdsBytes = 4096;
+constexpr uint32_t kBndBlockBytes = 1024;
+
+__device__ __forceinline__ uint2 lds_load8(const uint32_t *lds, uint32_t byte_off) {
+    return *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(lds) + byte_off);
+}
+__device__ __forceinline__ void lds_store8(uint32_t *lds, uint32_t byte_off, uint32_t h,
+                                           uint32_t e) {
+    *reinterpret_cast<uint2 *>(reinterpret_cast<char *>(lds) + byte_off) = make_uint2(h, e);
+}
+__device__ __forceinline__ uint4 lds_load16(const uint32_t *lds, uint32_t byte_off) {
+    return *reinterpret_cast<const uint4 *>(reinterpret_cast<const char *>(lds) + byte_off);
+}
+__device__ __forceinline__ void lds_store16(uint32_t *lds, uint32_t byte_off, uint4 v) {
+    *reinterpret_cast<uint4 *>(reinterpret_cast<char *>(lds) + byte_off) = v;
+}
+// Order this wave's LDS (and global) accesses across lanes: everything
+// before is complete before anything after starts.
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+}
 
 // DPP move of `v` from lane-1 to every lane (wave_shr:1), with `bnd` at
 // each group's first lane (l == 0), whatever the group width.
@@ -238,6 +295,12 @@ __device__ __forceinline__ PairRef load_pair(const KParams &P, int64_t pos, int6
     } else {
         r.q0 = q0; r.t0 = t0; r.m = (int32_t)m; r.n = (int32_t)n;
     }
+    // a column longer than one group's share of the slot cannot be held
+    if (r.n > P.max_rows) {
+        r.q0 = r.t0 = 0;
+        r.m = r.n = 0;
+        r.invalid = true;
+    }
     return r;
 }
 
@@ -292,6 +355,17 @@ __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr
     P.out_score[pr.id] = s;
     P.out_qend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)(key & 0xFFFF)) : -1;
     P.out_tend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF)) : -1;
+}
+
+// Per-request completion: count pair `id` as finished for its tag.  The
+// release at system scope makes the pair's outputs (this lane's stores
+// above) visible to the host before the count that announces them.
+__device__ __forceinline__ void signal_done(const KParams &P, int32_t id) {
+    if (P.pair_tag == nullptr || id < 0) return;
+    const int32_t tg = P.pair_tag[id];
+    if (tg >= 0)
+        __hip_atomic_fetch_add(P.tag_done + tg, 1u, __ATOMIC_RELEASE,
+                               __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // Trace pass: choice codes, one nibble per cell, as the fill stores them.
@@ -441,7 +515,7 @@ template <int K, int CT, bool REV, bool NM, bool BAND, bool TR>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                          BaseStream qm, BaseStream tm,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
-                         uint32_t *slot, uint32_t *lds_saved) {
+                         uint32_t *slot, uint32_t *lds_saved, uint32_t *lds_bnd) {
     const int G = kWave / W;
     constexpr bool PK = CT != kCellWide;
     constexpr int NPG = PK ? 2 : 1;
@@ -506,7 +580,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(-beta)) * 0x10001u;
 
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
-    const Slot bslot{slot};
+    const Slot bslot{slot, (uint32_t)P.slot_words * 4u};
     // trace pass: this group's share of the block's code slot; the pair's
     // codes take (its chunks) x n rows x W lanes x K/2 bytes, laid out
     // [chunk][row][lane] so that the group's stores of one step are
@@ -535,6 +609,14 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     // at most 64 groups keep every offset in 32 bits)
     const uint32_t row_bytes = (uint32_t)Gs * 8u;
     const uint32_t ld_lane = (uint32_t)gs * 8u;
+    // unbanded: the column in LDS, resident when the whole column fits, else
+    // through the rings (Gs is then a power of two, so a 1 KiB block holds
+    // SB = 128 / Gs whole rows)
+    const bool bnd_res = (uint32_t)R * row_bytes <= kBndLdsBytes;
+    const uint32_t bnd_mask = bnd_res ? 0xFFFFFFFFu : 2u * kBndBlockBytes - 1u;
+    const uint32_t bnd_wbase = bnd_res ? 0u : 2u * kBndBlockBytes;
+    const int sb_shift = __builtin_ctz(kBndBlockBytes / row_bytes);
+    const uint32_t lane16 = (uint32_t)lane * 16u;
 
     for (int c = 0; c < C; ++c) {
         const int col0 = c * W * K + l * K;
@@ -547,7 +629,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         const int bnd_hi = BAND ? min(R - 1, c0 - 1 + bw) : R - 1;
         auto slot_off = [&](int row) -> uint32_t {
             return row <= bnd_hi ? ld_lane + ((uint32_t)row & rwrap) * row_bytes
-                                 : (uint32_t)kSlotBytes;
+                                 : bslot.bytes;
         };
         // per-lane target stream geometry (per pair of the group)
         int64_t twi[NPG];
@@ -658,11 +740,29 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         const bool write_bnd = c + 1 < C;
         const bool first_lane = l == 0;
         const bool last_lane = l == W - 1 && mine;
-        uint2 fifo[4];
+        // banded: the boundary rows of the next four steps, in flight
+        uint2 fifo[BAND ? 4 : 1];
+        // unbanded: the boundary row of the current step (read one step
+        // ahead from LDS) and, in ring mode, the next block in flight
+        uint2 bnd_cur = make_uint2(0u, 0u);
+        uint4 inflight = make_uint4(0u, 0u, 0u, 0u);
+        if constexpr (BAND) {
 #pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            fifo[r] = make_uint2(0u, 0u);
-            if (have_bnd) fifo[r] = bslot.load(slot_off(r0 + r));
+            for (int r = 0; r < 4; ++r) {
+                fifo[r] = make_uint2(0u, 0u);
+                if (have_bnd) fifo[r] = bslot.load(slot_off(r0 + r));
+            }
+        } else if (have_bnd) {
+            if (!bnd_res) {
+                // blocks 0 and 1 into the read ring, then block 2 in flight
+                const uint4 b0 = bslot.load16(lane16);
+                const uint4 b1 = bslot.load16(kBndBlockBytes + lane16);
+                lds_store16(lds_bnd, lane16, b0);
+                lds_store16(lds_bnd, kBndBlockBytes + lane16, b1);
+                wave_sync();
+                inflight = bslot.load16(2u * kBndBlockBytes + lane16);
+            }
+            bnd_cur = lds_load8(lds_bnd, ld_lane);      // row 0 (R >= 1 here)
         }
         if constexpr (BAND) {
             // lane 0's first diagonal: H(r0 - 1, c0 - 1), inside the band
@@ -732,8 +832,30 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 const int s = s0 + j;
                 if (s < S) {
                 const int i = r0 + s - l;
-                const uint2 bnd = fifo[j & 3];
-                if (have_bnd) fifo[j & 3] = bslot.load(slot_off(r0 + s + 4));
+                uint2 bnd;
+                if constexpr (BAND) {
+                    bnd = fifo[j & 3];
+                    if (have_bnd) fifo[j & 3] = bslot.load(slot_off(r0 + s + 4));
+                } else {
+                    bnd = bnd_cur;
+                    if (have_bnd) {
+                        // row rn = s + 1 for the next step; when rn starts
+                        // block kb, block kb + 1 (in flight) goes into the
+                        // read ring in place of block kb - 1, and kb + 2 is
+                        // loaded (rows past the column read as 0)
+                        const int rn = s + 1;
+                        if (!bnd_res && (rn & ((1 << sb_shift) - 1)) == 0) {
+                            const uint32_t kb = (uint32_t)rn >> sb_shift;
+                            lds_store16(lds_bnd, ((kb + 1u) & 1u) * kBndBlockBytes + lane16,
+                                        inflight);
+                            asm volatile("" ::: "memory");
+                            inflight = bslot.load16((kb + 2u) * kBndBlockBytes + lane16);
+                        }
+                        bnd_cur = rn < R ? lds_load8(lds_bnd, (((uint32_t)rn * row_bytes) &
+                                                               bnd_mask) + ld_lane)
+                                         : make_uint2(0u, 0u);
+                    }
+                }
                 // banded: bit k set when column col0 + k of row i is in the band
                 uint32_t bmask = 0xFFFFFFFFu;
                 if constexpr (MASK) {
@@ -953,9 +1075,25 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 // the group's last lane holds row r0 + s - (W-1): one of the
                 // chunk's rows once s >= W-1 (and never past them, as
                 // s < nrows + W - 1)
-                if (write_bnd && s >= W - 1 && last_lane)
-                    bslot.store(ld_lane + ((uint32_t)(r0 + s - (W - 1)) & rwrap) * row_bytes,
-                                hout, eout);
+                if constexpr (BAND) {
+                    if (write_bnd && s >= W - 1 && last_lane)
+                        bslot.store(ld_lane + ((uint32_t)(r0 + s - (W - 1)) & rwrap) * row_bytes,
+                                    hout, eout);
+                } else if (write_bnd && s >= W - 1) {
+                    // row r of this chunk's column into LDS; in ring mode a
+                    // completed block goes to the slot as one burst
+                    const uint32_t r = (uint32_t)(s - (W - 1));
+                    if (last_lane)
+                        lds_store8(lds_bnd, bnd_wbase + ((r * row_bytes) & bnd_mask) + ld_lane,
+                                   hout, eout);
+                    if (!bnd_res && ((r + 1u) & ((1u << sb_shift) - 1u)) == 0) {
+                        asm volatile("" ::: "memory");
+                        const uint32_t kb = r >> sb_shift;
+                        const uint4 v = lds_load16(lds_bnd, bnd_wbase + (kb & 1u) * kBndBlockBytes +
+                                                               lane16);
+                        bslot.store16(kb * kBndBlockBytes + lane16, v);
+                    }
+                }
                 }  // s < S
             }
             };
@@ -973,6 +1111,14 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             run_steps(b, S, std::true_type{});
         } else {
             run_steps(0, S, std::false_type{});
+            // ring mode: the column's last, partial block goes to the slot
+            if (write_bnd && !bnd_res && ((uint32_t)R & ((1u << sb_shift) - 1u)) != 0) {
+                asm volatile("" ::: "memory");
+                const uint32_t kb = (uint32_t)R >> sb_shift;
+                const uint4 v =
+                    lds_load16(lds_bnd, bnd_wbase + (kb & 1u) * kBndBlockBytes + lane16);
+                bslot.store16(kb * kBndBlockBytes + lane16, v);
+            }
         }
 
         // resolve this chunk's candidate column per pair
@@ -1006,7 +1152,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             if (mine && l == (W > 1 ? h : 0))
                 trace_walk<K, PK>(P, pr[h], key, tr_codes, tr_fits, W, h, tr_rows, qs, ts);
         } else {
-            if (l == 0 && mine) write_result<REV>(P, pr[h], key);
+            if (l == 0 && mine) {
+                write_result<REV>(P, pr[h], key);
+                if constexpr (!REV) signal_done(P, pr[h].id);
+            }
         }
     }
 }
@@ -1034,7 +1183,7 @@ template <int K, bool REV, bool NM, bool BAND, bool TR>
 __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                              BaseStream qm, BaseStream tm,
                                              int64_t pos0, int npairs, int W, uint32_t *slot,
-                                             uint32_t *lds) {
+                                             uint32_t *lds, uint32_t *lds_bnd) {
     const int G = kWave / W;
     // rows one slot holds for G groups; larger units run one group at a time
     int rmax = 0;
@@ -1050,7 +1199,10 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     // groups whose boundary columns fit one slot together; a larger unit is
     // processed in several passes of that many groups.  One call site per
     // instantiation keeps run_unit inlined.
-    const int fit = (int)min<int64_t>(G, kSlotWords / (2 * (int64_t)max(rows, 1)));
+    int fit = (int)min<int64_t>(G, (int64_t)P.slot_words / (2 * (int64_t)max(rows, 1)));
+    // unbanded passes keep a power-of-two group count (the LDS ring's
+    // blocks hold whole rows); G is a power of two, so every pass is full
+    if (!BAND) fit = 1 << (31 - __builtin_clz((unsigned)fit));
     const int passes = (G + fit - 1) / fit;
     // with N masks the host turns binary16 cells off (their table cannot
     // give an N column the mismatch), so NM never instantiates them
@@ -1060,19 +1212,19 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
         if constexpr (!NM && !TR) {
             for (int ps = 0; ps < passes; ++ps)
                 run_unit<K, kCellF16, REV, false, BAND, false>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
-                                                  ps * fit, min(fit, G - ps * fit), W, slot, lds);
+                                                  ps * fit, min(fit, G - ps * fit), W, slot, lds, lds_bnd);
         }
     } else if (ct == kCellU16 || ct == kCellF16) {
         for (int ps = 0; ps < passes; ++ps)
             run_unit<K, kCellU16, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0, pos0 + npairs,
                                                      ps * fit, min(fit, G - ps * fit), W, slot,
-                                                     lds);
+                                                     lds, lds_bnd);
     } else {
         for (int it = 0; it < 2 * passes; ++it) {
             const int half = it / passes, ps = it % passes;
             run_unit<K, kCellWide, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0 + (int64_t)half * G,
                                             pos0 + npairs, ps * fit, min(fit, G - ps * fit), W,
-                                            slot, lds);
+                                            slot, lds, lds_bnd);
         }
     }
 }
@@ -1090,6 +1242,7 @@ constexpr int kMinWaves = TR ? (K <= 8 ? 3 : 2) : (K <= 16 ? 3 : 2);
 template <int K, bool NM>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM>, 8))) void plain_kernel(KParams P, int W) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_bnd[kBndLdsBytes / 4];
     BaseStream qs, ts, qm, tm;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
     ts.init(P.t_seqs, P.t_off, P.n_pairs);
@@ -1097,11 +1250,12 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
     tm.init_mask(P.t_nmask, P.t_off, P.n_pairs);
     const int ppu = 2 * (kWave / W);
     const int64_t n_units = (P.n_pairs + ppu - 1) / ppu;
-    uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
+    uint32_t *slot = P.scratch + (size_t)blockIdx.x * (size_t)P.slot_words;
     for (int64_t u = blockIdx.x; u < n_units; u += gridDim.x) {
         const int64_t pos0 = u * ppu;
         const int np = (int)min<int64_t>(ppu, P.n_pairs - pos0);
-        process_unit<K, false, NM, false, false>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved);
+        process_unit<K, false, NM, false, false>(P, qs, ts, qm, tm, pos0, np, W, slot, lds_saved,
+                                                 lds_bnd);
     }
 }
 
@@ -1119,14 +1273,18 @@ constexpr int kClaimStagger = 4;
 template <int K, bool REV, bool NM, bool BAND, bool TR>
 __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K, NM, TR>, 8))) void persistent_kernel(KParams P) {
     __shared__ __attribute__((aligned(16))) uint32_t lds_saved[kWave * 2 * K];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_bnd[kBndLdsBytes / 4];
     BaseStream qs, ts, qm, tm;
     qs.init(P.q_seqs, P.q_off, P.n_pairs);
     ts.init(P.t_seqs, P.t_off, P.n_pairs);
     qm.init_mask(P.q_nmask, P.q_off, P.n_pairs);
     tm.init_mask(P.t_nmask, P.t_off, P.n_pairs);
-    uint32_t *slot = P.scratch + (size_t)blockIdx.x * kSlotWords;
+    uint32_t *slot = P.scratch + (size_t)blockIdx.x * (size_t)P.slot_words;
     const int lane = threadIdx.x & (kWave - 1);
-    const int total = __builtin_amdgcn_readfirstlane(*P.total_units);
+    // this launch claims the units of the bins with K query columns per lane
+    constexpr int kc = K == 8 ? 0 : K == 16 ? 1 : 2;
+    int32_t *const counter = P.unit_counter + kc;
+    const int total = __builtin_amdgcn_readfirstlane(P.total_units[kc]);
     // Spread the first claims over the SIMDs.  The queue starts with the
     // costliest units; left to arrival order, the waves dispatched first
     // (several to a SIMD) take them, and a batch with fewer long units than
@@ -1141,19 +1299,19 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
         for (int k = 0; k < naps; ++k) {
             __builtin_amdgcn_s_sleep(127);
             const int claimed = __builtin_amdgcn_readfirstlane(
-                __hip_atomic_load(P.unit_counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+                __hip_atomic_load(counter, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
             if (claimed >= total) break;
         }
     }
     for (;;) {
         int u = 0;
-        if (lane == 0) u = atomicAdd(P.unit_counter, 1);
+        if (lane == 0) u = atomicAdd(counter, 1);
         u = __builtin_amdgcn_readfirstlane(__shfl(u, 0, kWave));
         if (u >= total) break;
         int b = 0;
         for (int k = 0; k < kMaxBins; ++k) {
             const int u0 = P.bins[k].unit0, nu = P.bins[k].units;
-            if (u >= u0 && u < u0 + nu) b = k;
+            if (P.bins[k].cols == K && u >= u0 && u < u0 + nu) b = k;
         }
         b = __builtin_amdgcn_readfirstlane(b);
         const BinDesc &bd = P.bins[b];
@@ -1163,7 +1321,8 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
         const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
         const int64_t pos0 = first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
-        process_unit<K, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved);
+        process_unit<K, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved,
+                                           lds_bnd);
     }
 }
 

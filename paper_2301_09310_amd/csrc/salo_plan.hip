@@ -75,7 +75,7 @@ __device__ __forceinline__ int pair_bin(const KParams &P, const BinTable &bt, in
     for (int b = 0; b < bt.n_bins; ++b) {
         if (bt.packed[b] != want) continue;
         last = b;
-        const int64_t row_cap = kSlotWords * (int64_t)bt.lanes[b] / (2 * 64);
+        const int64_t row_cap = (int64_t)P.slot_words * bt.lanes[b] / (2 * 64);
         if (m <= bt.m_hi[b] && n <= row_cap) return b;
     }
     return last;
@@ -95,7 +95,7 @@ __global__ void plan_zero(PlanBuffers pb, int32_t *counters) {
         pb.binstat[3 * i + 1] = 0x7FFFFFFF;
         pb.binstat[3 * i + 2] = 0;
     }
-    if (i < 4) counters[i] = 0;
+    if (i < kCounterWords) counters[i] = 0;
 }
 
 __global__ __launch_bounds__(kTpb) void plan_bins(KParams P, BinTable bt, PlanBuffers pb) {
@@ -193,8 +193,9 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_top(KParams P, BinTabl
         run += loc[k];
     }
     if (t == 0) {
-        // bins appear in descending index order in the sorted list
-        int32_t first = 0, unit0 = 0;
+        // bins appear in descending index order in the sorted list; units
+        // are numbered within each bin's column class
+        int32_t first = 0, unit0[kColClasses] = {0, 0, 0};
         for (int b = kMaxBins - 1; b >= 0; --b) {
             BinDesc d;
             const bool on = b < bt.n_bins;
@@ -205,15 +206,18 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_top(KParams P, BinTabl
             d.count = on ? pb.binstat[3 * b + 0] : 0;
             d.first = first;
             d.units = (d.count + d.pairs - 1) / d.pairs;
-            d.unit0 = unit0;
+            const int kc = col_class(d.cols);
+            d.unit0 = unit0[kc];
             d.n_min = on ? pb.binstat[3 * b + 1] : 0;
             d.n_max = on ? pb.binstat[3 * b + 2] : 0;
             first += d.count;
-            unit0 += d.units;
+            unit0[kc] += d.units;
             P.bins[b] = d;
         }
-        *P.total_units = unit0;
-        *P.unit_counter = 0;
+        for (int kc = 0; kc < kColClasses; ++kc) {
+            P.total_units[kc] = unit0[kc];
+            P.unit_counter[kc] = 0;
+        }
     }
 }
 

@@ -24,6 +24,8 @@ with L = 1 for single-base indels or L ~ Geometric(1/2) (mean 2).
 from __future__ import annotations
 
 import hashlib
+import os
+from concurrent.futures import ThreadPoolExecutor
 from dataclasses import dataclass
 
 import numpy as np
@@ -254,6 +256,33 @@ def _build_targets(rng, src, src_lens, left, right):
 CHUNK_PAIRS = 100_000   # part of the generator definition (fixes the seeds)
 
 
+def _chunked(n_pairs: int, make, progress=None, workers: int = 0):
+    """Run make(c0, n) for every chunk of CHUNK_PAIRS pairs and assemble the
+    parts in chunk order.  Each chunk draws from its own seeded generator,
+    so the batch is the same whatever the number of worker threads (numpy
+    releases the interpreter lock in its bulk loops)."""
+    starts = list(range(0, n_pairs, CHUNK_PAIRS))
+    if workers <= 0:
+        workers = min(8, os.cpu_count() or 1)
+    parts = [None] * len(starts)
+
+    def one(k):
+        c0 = starts[k]
+        parts[k] = make(c0, min(CHUNK_PAIRS, n_pairs - c0))
+
+    if workers == 1 or len(starts) <= 1:
+        for k, c0 in enumerate(starts):
+            if progress is not None:
+                progress(c0, n_pairs)
+            one(k)
+    else:
+        with ThreadPoolExecutor(max_workers=workers) as ex:
+            for k, _ in enumerate(ex.map(one, range(len(starts)))):
+                if progress is not None:
+                    progress(starts[k], n_pairs)
+    return _assemble([p[0] for p in parts], [p[1] for p in parts])
+
+
 def plain_small(seed: int = 0, n_pairs: int = 1000) -> Batch:
     """Parity workload: 1,000 pairs; target = 250 random bases; query = 150
     bases emitted by walking the target from a uniform start in [0, 90]
@@ -278,16 +307,13 @@ def plain_small(seed: int = 0, n_pairs: int = 1000) -> Batch:
     return b
 
 
-def short_reads(seed: int = 0, n_pairs: int = 2_000_000, progress=None) -> Batch:
+def short_reads(seed: int = 0, n_pairs: int = 2_000_000, progress=None,
+                workers: int = 0) -> Batch:
     """Short-read extension: source length U{50..250}; target = source plus
     a U{0..100} flank split at random into left/right; query = source with
     1% substitutions and 0.1% single-base indels; 10% of pairs are
     unrelated random sequences of the same lengths."""
-    q_parts, t_parts = [], []
-    for c0 in range(0, n_pairs, CHUNK_PAIRS):
-        n = min(CHUNK_PAIRS, n_pairs - c0)
-        if progress is not None:
-            progress(c0, n_pairs)
+    def chunk(c0, n):
         rng = np.random.default_rng([seed, 2, c0 // CHUNK_PAIRS])
         src_lens = rng.integers(50, 251, n).astype(np.int64)
         flank = rng.integers(0, 101, n).astype(np.int64)
@@ -305,23 +331,20 @@ def short_reads(seed: int = 0, n_pairs: int = 2_000_000, progress=None) -> Batch
             mq[qmask] = _rand_bases(rng, qmask.sum())
             t[tmask] = _rand_bases(rng, tmask.sum())
             del qo, to
-        q_parts.append((mq, ml))
-        t_parts.append((t, tl))
-    b = _assemble(q_parts, t_parts)
+        return (mq, ml), (t, tl)
+
+    b = _chunked(n_pairs, chunk, progress, workers)
     b.name = "short_reads"
     return b
 
 
-def long_uneven(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch:
+def long_uneven(seed: int = 0, n_pairs: int = 200_000, progress=None,
+                workers: int = 0) -> Batch:
     """Long uneven extension: source length round(exp(U[ln 500, ln 5000]));
     target length round(source * U[1.1, 1.5]) with the source at a random
     offset; query = source with 5% substitutions and 3% indels of geometric
     length (mean 2)."""
-    q_parts, t_parts = [], []
-    for c0 in range(0, n_pairs, CHUNK_PAIRS):
-        n = min(CHUNK_PAIRS, n_pairs - c0)
-        if progress is not None:
-            progress(c0, n_pairs)
+    def chunk(c0, n):
         rng = np.random.default_rng([seed, 3, c0 // CHUNK_PAIRS])
         src_lens = np.rint(np.exp(rng.uniform(np.log(500), np.log(5000), n))).astype(np.int64)
         tl = np.rint(src_lens * rng.uniform(1.1, 1.5, n)).astype(np.int64)
@@ -329,14 +352,15 @@ def long_uneven(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch:
         src = _rand_bases(rng, src_lens.sum())
         t, tl = _build_targets(rng, src, src_lens, left, right)
         mq, ml = _mutate(rng, src, src_lens, 0.05, 0.03, geometric=True)
-        q_parts.append((mq, ml))
-        t_parts.append((t, tl))
-    b = _assemble(q_parts, t_parts)
+        return (mq, ml), (t, tl)
+
+    b = _chunked(n_pairs, chunk, progress, workers)
     b.name = "long_uneven"
     return b
 
 
-def anchored_long(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch:
+def anchored_long(seed: int = 0, n_pairs: int = 200_000, progress=None,
+                  workers: int = 0) -> Batch:
     """Anchored long extension, the input of banded extension: the long
     uneven workload's lengths and error model (source length
     round(exp(U[ln 500, ln 5000])), target length round(source *
@@ -344,11 +368,7 @@ def anchored_long(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch
     but with the source at target offset 0, as when both sequences start at
     the end of a seed: the best path starts near cell (0, 0) and stays near
     the main diagonal."""
-    q_parts, t_parts = [], []
-    for c0 in range(0, n_pairs, CHUNK_PAIRS):
-        n = min(CHUNK_PAIRS, n_pairs - c0)
-        if progress is not None:
-            progress(c0, n_pairs)
+    def chunk(c0, n):
         rng = np.random.default_rng([seed, 6, c0 // CHUNK_PAIRS])
         src_lens = np.rint(np.exp(rng.uniform(np.log(500), np.log(5000), n))).astype(np.int64)
         tl = np.rint(src_lens * rng.uniform(1.1, 1.5, n)).astype(np.int64)
@@ -357,9 +377,9 @@ def anchored_long(seed: int = 0, n_pairs: int = 200_000, progress=None) -> Batch
         src = _rand_bases(rng, src_lens.sum())
         t, tl = _build_targets(rng, src, src_lens, left, right)
         mq, ml = _mutate(rng, src, src_lens, 0.05, 0.03, geometric=True)
-        q_parts.append((mq, ml))
-        t_parts.append((t, tl))
-    b = _assemble(q_parts, t_parts)
+        return (mq, ml), (t, tl)
+
+    b = _chunked(n_pairs, chunk, progress, workers)
     b.name = "anchored_long"
     return b
 
@@ -376,16 +396,13 @@ def band_cells(q_lens, t_lens, band: int) -> np.ndarray:
     return total
 
 
-def mixed(seed: int = 0, n_pairs: int = 4_000_000, progress=None) -> Batch:
+def mixed(seed: int = 0, n_pairs: int = 4_000_000, progress=None,
+          workers: int = 0) -> Batch:
     """Batched mixed workload: source length drawn from a mixture of
     60% U{100..300}, 35% U{300..1000}, 5% U{1000..10000}; target length
     round(1.2 * source) with the source at a random offset; query = source
     with 2% substitutions and 1% single-base indels."""
-    q_parts, t_parts = [], []
-    for c0 in range(0, n_pairs, CHUNK_PAIRS):
-        n = min(CHUNK_PAIRS, n_pairs - c0)
-        if progress is not None:
-            progress(c0, n_pairs)
+    def chunk(c0, n):
         rng = np.random.default_rng([seed, 4, c0 // CHUNK_PAIRS])
         src_lens = mixed_lengths(rng, n)
         tl = np.rint(1.2 * src_lens).astype(np.int64)
@@ -393,9 +410,9 @@ def mixed(seed: int = 0, n_pairs: int = 4_000_000, progress=None) -> Batch:
         src = _rand_bases(rng, src_lens.sum())
         t, tl = _build_targets(rng, src, src_lens, left, right)
         mq, ml = _mutate(rng, src, src_lens, 0.02, 0.01, geometric=False)
-        q_parts.append((mq, ml))
-        t_parts.append((t, tl))
-    b = _assemble(q_parts, t_parts)
+        return (mq, ml), (t, tl)
+
+    b = _chunked(n_pairs, chunk, progress, workers)
     b.name = "mixed"
     return b
 

@@ -40,7 +40,7 @@ class Options(ctypes.Structure):
 
 class Bin(ctypes.Structure):
     _fields_ = [("m_hi", ctypes.c_int32), ("packed", ctypes.c_int32),
-                ("lanes", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("lanes", ctypes.c_int32), ("cols", ctypes.c_int32)]
 
 
 _lock = threading.Lock()
@@ -95,6 +95,13 @@ def load(path: str | None = None):
         lib.salo_align_trace.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp, vp,
                                          vp, vp, vp, i64, vp, ctypes.POINTER(Options)]
         lib.salo_align_trace.restype = i32
+        lib.salo_align_batch_tagged.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp,
+                                                vp, ctypes.POINTER(Options)]
+        lib.salo_align_batch_tagged.restype = i32
+        lib.salo_host_alloc.argtypes = [i64, ctypes.POINTER(vp)]
+        lib.salo_host_alloc.restype = i32
+        lib.salo_host_free.argtypes = [vp]
+        lib.salo_host_free.restype = i32
         if path is None:
             _lib = lib
         return lib
@@ -142,7 +149,8 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
     int64 CUDA tensors of n_pairs+1 entries.  Returns (score, q_end, t_end)
     int32 CUDA tensors (or fills `out`, a triple of such tensors).
     q_nmask / t_nmask: optional int32 CUDA tensors, one bit per base marking
-    N (salo_align_batch_n).  Keyword
+    N (salo_align_batch_n).  With no options and no masks the call goes
+    to salo_align_batch itself, else to salo_align_batch_ex.  Keyword
     options: mode ('auto' | 'plain' | 'persistent'), lanes, cols,
     force_int32, no_f16, waves_per_cu, timing.
     """
@@ -162,7 +170,12 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
     sc = Scoring(*[int(x) for x in scoring])
     opts = make_options(**options)
     qm, tm = _mask_arg(q_nmask, "q_nmask"), _mask_arg(t_nmask, "t_nmask")
-    if qm is None and tm is None:
+    if qm is None and tm is None and not options:
+        # default options: the plain entry point of the ABI
+        st = lib.salo_align_batch(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                                  t_offsets.data_ptr(), n, sc, out[0].data_ptr(),
+                                  out[1].data_ptr(), out[2].data_ptr(), _stream_handle(stream))
+    elif qm is None and tm is None:
         st = lib.salo_align_batch_ex(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
                                      t_offsets.data_ptr(), n, sc, out[0].data_ptr(),
                                      out[1].data_ptr(), out[2].data_ptr(),
@@ -174,6 +187,55 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
                                     _stream_handle(stream), ctypes.byref(opts))
     _check(lib, st)
     return out
+
+
+def align_batch_tagged(q_seqs, q_offsets, t_seqs, t_offsets, scoring, out_ptrs, pair_tag,
+                       tag_done_ptr, stream=None, **options):
+    """salo_align_batch_tagged: align_batch whose pair p adds 1 to the host
+    counter tag_done[pair_tag[p]] once its outputs are written.  out_ptrs:
+    three addresses of int32 [n_pairs] outputs (device memory or
+    host_alloc memory); pair_tag: int32 CUDA tensor [n_pairs];
+    tag_done_ptr: address of host_alloc memory holding the counters."""
+    import torch
+    lib = load()
+    n = _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets)
+    if not pair_tag.is_cuda or pair_tag.dtype != torch.int32 or pair_tag.numel() < n:
+        raise ValueError("pair_tag must be an int32 CUDA tensor of n_pairs entries")
+    opts = make_options(**options)
+    st = lib.salo_align_batch_tagged(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
+                                     t_offsets.data_ptr(), n, Scoring(*[int(x) for x in scoring]),
+                                     out_ptrs[0], out_ptrs[1], out_ptrs[2], pair_tag.data_ptr(),
+                                     tag_done_ptr, _stream_handle(stream), ctypes.byref(opts))
+    _check(lib, st)
+
+
+class HostBuffer:
+    """Host memory from salo_host_alloc (coherent for host and device), as a
+    numpy array of `count` elements of `dtype`; freed by free() or when
+    collected."""
+
+    def __init__(self, count: int, dtype):
+        import numpy as np
+        lib = load()
+        self.dtype = np.dtype(dtype)
+        self.nbytes = max(int(count) * self.dtype.itemsize, 4)
+        p = ctypes.c_void_p(0)
+        _check(lib, lib.salo_host_alloc(self.nbytes, ctypes.byref(p)))
+        self.ptr = int(p.value)
+        buf = (ctypes.c_uint8 * self.nbytes).from_address(self.ptr)
+        self.array = np.frombuffer(buf, dtype=self.dtype, count=int(count))
+
+    def free(self):
+        if self.ptr:
+            self.array = None
+            load().salo_host_free(ctypes.c_void_p(self.ptr))
+            self.ptr = 0
+
+    def __del__(self):
+        try:
+            self.free()
+        except Exception:
+            pass
 
 
 def _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets):
@@ -240,27 +302,43 @@ def align_trace(q_seqs, q_offsets, t_seqs, t_offsets, answers, starts, scoring=(
         if not t.is_cuda or t.dtype != torch.int32 or not t.is_contiguous() or t.numel() != n:
             raise ValueError("answers and starts must be contiguous int32 CUDA tensors")
     dev = q_offsets.device
-    if cig_off is None:
-        cig_off = cigar_offsets(q_offsets, t_offsets)
-    if out is None:
-        total = int(cig_off[-1].item()) if n > 0 else 0
-        cig = torch.zeros(max(total, 1), dtype=torch.int32, device=dev)
-        cig_len = torch.empty(max(n, 0), dtype=torch.int32, device=dev)
-    else:
-        cig, cig_len = out
-        if cig.dtype != torch.int32 or cig_len.dtype != torch.int32 or \
-                not cig.is_contiguous() or cig_len.numel() != n:
-            raise ValueError("out must be (int32 cig, int32 cig_len of n_pairs) CUDA tensors")
-    if workspace is None:
-        workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=dev)
+    # buffers made here are made, and their contents computed, on the
+    # launch stream, after the work the current stream has queued (which
+    # produced the inputs); each is marked as used by that stream, so the
+    # caching allocator cannot hand it to other work while the kernel runs
+    launch = stream if stream is not None else torch.cuda.current_stream(dev)
+    made = []
+    if launch != torch.cuda.current_stream(dev):
+        launch.wait_stream(torch.cuda.current_stream(dev))
+    with torch.cuda.stream(launch):
+        if cig_off is None:
+            cig_off = cigar_offsets(q_offsets, t_offsets)
+            made.append(cig_off)
+        if out is None:
+            total = int(cig_off[-1].item()) if n > 0 else 0
+            cig = torch.zeros(max(total, 1), dtype=torch.int32, device=dev)
+            cig_len = torch.empty(max(n, 0), dtype=torch.int32, device=dev)
+            made += [cig, cig_len]
+        else:
+            cig, cig_len = out
+            if cig.dtype != torch.int32 or cig_len.dtype != torch.int32 or \
+                    not cig.is_contiguous() or cig_len.numel() != n:
+                raise ValueError("out must be (int32 cig, int32 cig_len of n_pairs) CUDA "
+                                 "tensors")
+        if workspace is None:
+            workspace = torch.empty(int(workspace_bytes), dtype=torch.uint8, device=dev)
+            made.append(workspace)
     sc = Scoring(*[int(x) for x in scoring])
     opts = make_options(**options)
     st = lib.salo_align_trace(q_seqs.data_ptr(), q_offsets.data_ptr(), t_seqs.data_ptr(),
                               t_offsets.data_ptr(), n, sc, *(x.data_ptr() for x in arrs),
                               cig_off.data_ptr(), cig.data_ptr(), cig_len.data_ptr(),
-                              workspace.data_ptr(), workspace.numel(), _stream_handle(stream),
+                              workspace.data_ptr(), workspace.numel(), _stream_handle(launch),
                               ctypes.byref(opts))
     _check(lib, st)
+    if launch != torch.cuda.current_stream(dev):
+        for t in made:
+            t.record_stream(launch)
     return cig_off, cig, cig_len
 
 
@@ -311,22 +389,26 @@ def last_timing(stream=None):
 
 
 def set_bins(bins):
-    """Install a bin table: a list of (m_hi, packed, lanes); None restores
-    the built-in table."""
+    """Install a bin table: a list of (m_hi, packed, lanes[, cols]) (cols:
+    query columns per lane, 8/16/32, 0 or absent for 16); None restores the
+    built-in table."""
     lib = load()
     if bins is None:
         _check(lib, lib.salo_set_bins(None, 0))
         return
-    arr = (Bin * len(bins))(*[Bin(int(m), int(p), int(w), 0) for m, p, w in bins])
+    arr = (Bin * len(bins))(*[Bin(int(b[0]), int(b[1]), int(b[2]),
+                                  int(b[3]) if len(b) > 3 else 0) for b in bins])
     _check(lib, lib.salo_set_bins(arr, len(bins)))
 
 
 def get_bins():
+    """The current bin table as (m_hi, packed, lanes, cols) tuples."""
     lib = load()
     arr = (Bin * 16)()
     n = ctypes.c_int32(0)
     _check(lib, lib.salo_get_bins(arr, 16, ctypes.byref(n)))
-    return [(arr[i].m_hi, arr[i].packed, arr[i].lanes) for i in range(n.value)]
+    return [(arr[i].m_hi, arr[i].packed, arr[i].lanes, arr[i].cols or 16)
+            for i in range(n.value)]
 
 
 def load_tune_table(path: str) -> None:
@@ -334,7 +416,7 @@ def load_tune_table(path: str) -> None:
     import json
     with open(path) as f:
         t = json.load(f)
-    set_bins([(b["m_hi"], b["packed"], b["lanes"]) for b in t["bins"]])
+    set_bins([(b["m_hi"], b["packed"], b["lanes"], b.get("cols", 0)) for b in t["bins"]])
 
 
 def pack_bases(chars, offsets=None, revcomp: bool = False, out=None, invalid=None,

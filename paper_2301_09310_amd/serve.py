@@ -17,11 +17,19 @@ byte-aligned into the slot's pinned staging buffers, its offsets are
 shifted by the byte position, and one pad pair after each request (its
 query and target are the few padding bases up to the next request's
 first sequences) keeps the merged offsets contiguous; its output is
-dropped.  Staging and device buffers are
-allocated once per slot, so the steady state allocates nothing.  Results
-return to pinned host memory; completion is observed through one HIP
-event per launch.  Latency is measured from each request's scheduled
-arrival (open loop, so a slow server cannot hide queueing delay).
+dropped.  Staging and device buffers (the slot's device arena: sequences,
+offsets and the pair-to-request tags) are allocated once per slot, so the
+steady state allocates nothing.
+
+Completion is per request: the launch goes through salo_align_batch_tagged,
+whose kernel writes each pair's answers straight into the slot's host
+result buffer (host memory the device writes coherently) and then adds 1
+to its request's counter there.  The loop polls the counters and hands a
+request its results as soon as its own pairs are done, while the rest of
+the merged launch still runs; the slot itself is reused when the whole
+launch has ended (one HIP event).  Latency is measured from each request's
+scheduled arrival (open loop, so a slow server cannot hide queueing
+delay).
 
 The control plane (admission, FIFO order, launch forming, accounting) only
 talks to an executor object, so it runs on the CPU with a fake executor
@@ -95,11 +103,14 @@ class Merged:
 
 class GpuExecutor:
     """Runs launches on `n_slots` HIP streams, each with buffers sized for
-    `max_pairs` pairs and `max_bytes` packed bytes per sequence stream."""
+    `max_pairs` pairs and `max_bytes` packed bytes per sequence stream.
+    per_request: signal each request's completion as its own pairs finish
+    (salo_align_batch_tagged); otherwise the launch's end completes all of
+    its requests."""
 
     def __init__(self, n_slots: int = 3, max_pairs: int = 1 << 17,
                  max_bytes: int = 96 << 20, scoring=(1, -4, 6, 1), device="cuda",
-                 **options):
+                 per_request: bool = True, **options):
         import torch
         from paper_2301_09310_amd import salo
         salo.load()
@@ -107,6 +118,7 @@ class GpuExecutor:
         self.device = torch.device(device)
         self.scoring = scoring
         self.options = options
+        self.per_request = per_request
         self.max_pairs = int(max_pairs)
         self.max_bytes = int(max_bytes)
         self.slots = []
@@ -115,13 +127,21 @@ class GpuExecutor:
             host = {"q": torch.empty(self.max_bytes, dtype=torch.uint8, pin_memory=True),
                     "t": torch.empty(self.max_bytes, dtype=torch.uint8, pin_memory=True),
                     "qo": torch.empty(self.max_pairs + 1, dtype=torch.int64, pin_memory=True),
-                    "to": torch.empty(self.max_pairs + 1, dtype=torch.int64, pin_memory=True),
-                    "out": torch.empty((3, self.max_pairs), dtype=torch.int32,
-                                       pin_memory=True)}
+                    "to": torch.empty(self.max_pairs + 1, dtype=torch.int64, pin_memory=True)}
+            if per_request:
+                host["tag"] = torch.empty(self.max_pairs, dtype=torch.int32, pin_memory=True)
+            else:
+                host["out"] = torch.empty((3, self.max_pairs), dtype=torch.int32,
+                                          pin_memory=True)
             dev = {k: torch.empty_like(v, device=self.device) for k, v in host.items()}
+            slot = {"stream": s, "host": host, "dev": dev, "event": torch.cuda.Event()}
+            if per_request:
+                # results and per-request counters in coherent host memory:
+                # the kernel writes them, the loop reads them while it runs
+                slot["res"] = salo.HostBuffer(3 * self.max_pairs, np.int32)
+                slot["done"] = salo.HostBuffer(self.max_pairs, np.uint32)
             salo.reserve(self.max_pairs, stream=s)
-            self.slots.append({"stream": s, "host": host, "dev": dev,
-                               "event": torch.cuda.Event()})
+            self.slots.append(slot)
         self.free = list(range(n_slots))
 
     @property
@@ -141,30 +161,71 @@ class GpuExecutor:
         h, d, s = sl["host"], sl["dev"], sl["stream"]
         n = m.n_pairs
         starts = m.fill(h["q"].numpy(), h["qo"].numpy(), h["t"].numpy(), h["to"].numpy())
+        if self.per_request:
+            tag = h["tag"].numpy()
+            for i, (r, p) in enumerate(zip(reqs, starts)):
+                tag[p:p + r.batch.n_pairs] = i
+                tag[p + r.batch.n_pairs] = -1          # the pad pair after the request
+            sl["done"].array[:len(reqs)] = 0
+        # the stream waits for the previous launch on this slot before the
+        # staging copies overwrite its device buffers (stream order)
         with torch.cuda.stream(s):
             d["q"][:m.q_bytes].copy_(h["q"][:m.q_bytes], non_blocking=True)
             d["t"][:m.t_bytes].copy_(h["t"][:m.t_bytes], non_blocking=True)
             d["qo"][:n + 1].copy_(h["qo"][:n + 1], non_blocking=True)
             d["to"][:n + 1].copy_(h["to"][:n + 1], non_blocking=True)
-            out = (d["out"][0, :n], d["out"][1, :n], d["out"][2, :n])
-            self.salo.align_batch(d["q"][:m.q_bytes], d["qo"][:n + 1], d["t"][:m.t_bytes],
-                                  d["to"][:n + 1], self.scoring, out=out, stream=s,
-                                  **self.options)
-            for c in range(3):
-                h["out"][c, :n].copy_(d["out"][c, :n], non_blocking=True)
+            if self.per_request:
+                d["tag"][:n].copy_(h["tag"][:n], non_blocking=True)
+                base = sl["res"].ptr
+                outs = (base, base + 4 * self.max_pairs, base + 8 * self.max_pairs)
+                self.salo.align_batch_tagged(d["q"][:m.q_bytes], d["qo"][:n + 1],
+                                             d["t"][:m.t_bytes], d["to"][:n + 1], self.scoring,
+                                             outs, d["tag"], sl["done"].ptr, stream=s,
+                                             **self.options)
+            else:
+                out = (d["out"][0, :n], d["out"][1, :n], d["out"][2, :n])
+                self.salo.align_batch(d["q"][:m.q_bytes], d["qo"][:n + 1], d["t"][:m.t_bytes],
+                                      d["to"][:n + 1], self.scoring, out=out, stream=s,
+                                      **self.options)
+                for c in range(3):
+                    h["out"][c, :n].copy_(d["out"][c, :n], non_blocking=True)
             sl["event"].record(s)
-        return (k, [(r, p) for r, p in zip(reqs, starts)])
+        return (k, [(r, p) for r, p in zip(reqs, starts)], set())
+
+    def _result(self, sl, r, p):
+        if self.per_request:
+            res = sl["res"].array
+            n = r.batch.n_pairs
+            mp = self.max_pairs
+            return tuple(res[c * mp + p:c * mp + p + n].copy() for c in range(3))
+        out = sl["host"]["out"].numpy()
+        return tuple(out[c, p:p + r.batch.n_pairs].copy() for c in range(3))
+
+    def poll_requests(self, handle):
+        """Requests of a running launch whose pairs have all finished since
+        the last poll: [(index in the launch, result)]."""
+        if not self.per_request:
+            return []
+        k, parts, reported = handle
+        sl = self.slots[k]
+        done = sl["done"].array
+        out = []
+        for i, (r, p) in enumerate(parts):
+            if i not in reported and int(done[i]) == r.batch.n_pairs:
+                reported.add(i)
+                out.append((i, self._result(sl, r, p)))
+        return out
 
     def poll(self, handle) -> bool:
         return self.slots[handle[0]]["event"].query()
 
     def collect(self, handle):
-        k, parts = handle
+        """Wait for the launch's end, free its slot and return every
+        request's result."""
+        k, parts, _ = handle
         sl = self.slots[k]
         sl["event"].synchronize()
-        out = sl["host"]["out"].numpy()
-        res = [tuple(out[c, p:p + r.batch.n_pairs].copy() for c in range(3))
-               for r, p in parts]
+        res = [self._result(sl, r, p) for r, p in parts]
         self.free.append(k)
         return res
 
@@ -257,16 +318,24 @@ class Server:
             while nxt < len(reqs) and reqs[nxt].arrival <= now:
                 pending.append(reqs[nxt])
                 nxt += 1
-            # completions
+            # completions: requests whose own pairs are done (executors that
+            # signal per request), then whole launches
             still = []
+            per_req = getattr(self.ex, "poll_requests", None)
             for handle, group in inflight:
+                if per_req is not None:
+                    for i, res in per_req(handle):
+                        r = group[i]
+                        r.result, r.t_done, r.status = res, self.clock(), "done"
+                        done_count += 1
                 if self.ex.poll(handle):
                     results = self.ex.collect(handle)
                     t_done = self.clock()
                     for r, res in zip(group, results):
-                        r.result, r.t_done, r.status = res, t_done, "done"
+                        if r.status != "done":
+                            r.result, r.t_done, r.status = res, t_done, "done"
+                            done_count += 1
                         in_bytes -= r.footprint
-                    done_count += len(group)
                 else:
                     still.append((handle, group))
             inflight = still
@@ -319,6 +388,13 @@ def poisson_arrivals(n: int, rate: float, seed: int) -> np.ndarray:
 def request_sizes(n: int, seed: int, max_pairs: int = 4096) -> np.ndarray:
     rng = np.random.default_rng([seed, 10])
     return rng.integers(1, max_pairs + 1, n)
+
+
+def with_arrivals(requests, arrivals):
+    """Fresh requests sharing the batches of `requests`, with new arrival
+    times (the same requests replayed at another offered rate)."""
+    return [Request(rid=r.rid, batch=r.batch, arrival=float(t))
+            for r, t in zip(requests, arrivals)]
 
 
 def split_requests(pool, sizes, arrivals):

@@ -101,9 +101,12 @@ def test_too_many_pairs(lib):
 def test_bin_table_roundtrip(lib):
     default = salo.get_bins()
     assert default[-1][0] == 65535 and len(default) >= 2
-    table = [(100, 1, 1), (1000, 1, 4), (65535, 1, 16), (65535, 0, 8)]
+    table = [(100, 1, 1, 8), (1000, 1, 4, 32), (65535, 1, 16, 16), (65535, 0, 8, 16)]
     salo.set_bins(table)
     assert salo.get_bins() == table
+    # three-field entries take 16 columns per lane
+    salo.set_bins([(t[0], t[1], t[2]) for t in table])
+    assert salo.get_bins() == [(t[0], t[1], t[2], 16) for t in table]
     salo.set_bins(None)
     assert salo.get_bins() == default
 
@@ -113,6 +116,7 @@ def test_bin_table_roundtrip(lib):
     [(100, 1, 1), (50, 1, 4), (65535, 1, 4), (65535, 0, 8)],  # m_hi decreasing
     [(100, 1, 1), (65535, 0, 8)],                          # 16-bit kind not closed
     [(65535, 1, 1)],                                       # no 32-bit kind
+    [(100, 1, 1, 12), (65535, 1, 4), (65535, 0, 8)],      # columns not 8, 16 or 32
 ])
 def test_bad_bin_tables(lib, table):
     before = salo.get_bins()

@@ -276,7 +276,12 @@ def test_bin_table_does_not_change_results(dev):
     try:
         for table in ([(300, 1, 64), (65535, 1, 1), (65535, 0, 2)],
                       [(50, 1, 8), (100, 1, 1), (400, 1, 32), (65535, 1, 4), (500, 0, 64),
-                       (65535, 0, 1)]):
+                       (65535, 0, 1)],
+                      # a column count per bin: one persistent launch per class
+                      [(64, 1, 4, 8), (200, 1, 2, 32), (800, 1, 16, 16), (65535, 1, 64, 8),
+                       (300, 0, 8, 32), (65535, 0, 32, 8)],
+                      [(128, 1, 1, 32), (1024, 1, 8, 8), (65535, 1, 32, 32),
+                       (65535, 0, 4, 16)]):
             salo.set_bins(table)
             _say("bin table", table)
             assert_same(b, gpu_align(b), want, "table %s" % (table,))
@@ -395,3 +400,66 @@ def test_graph_capture_all_passes(dev):
         cg = cig.cpu().numpy().view(np.uint32)
         for p in np.nonzero(wln > 0)[0]:
             assert np.array_equal(cg[off[p]:off[p] + ln[p]], wcig[woff[p]:woff[p] + wln[p]])
+
+
+def test_capture_on_unreserved_stream_is_refused(dev):
+    """A first call on a stream made under graph capture cannot create its
+    workspace: it returns SALO_ERR_CAPTURE and enqueues nothing, and an
+    eager call on the same stream afterwards works and is exact."""
+    import torch
+    from paper_2301_09310_amd import salo
+    b = I.random_pairs(53, 800, 400, related=0.6)
+    want = oracle_align(b)
+    s = torch.cuda.Stream()
+    q, qo, t, to = salo.to_device(b)
+    out = tuple(torch.full((b.n_pairs,), -9, dtype=torch.int32, device="cuda")
+                for _ in range(3))
+    torch.cuda.synchronize()
+    _say("capture on an unreserved stream")
+    g = torch.cuda.CUDAGraph()
+    with pytest.raises(salo.SaloError) as err:
+        with torch.cuda.graph(g, stream=s):
+            salo.align_batch(q, qo, t, to, out=out, stream=s)
+    assert err.value.status == -4
+    torch.cuda.synchronize()
+    assert all(bool((x == -9).all()) for x in out)
+    with torch.cuda.stream(s):
+        salo.align_batch(q, qo, t, to, out=out, stream=s)
+    s.synchronize()
+    got = tuple(x.cpu().numpy().astype(np.int64) for x in out)
+    assert_same(b, got, want, "eager after a refused capture")
+
+
+def test_growth_after_capture_keeps_the_graph_valid(dev):
+    """A graph captured on a stream keeps working after a larger eager call
+    on that stream has grown the workspace (the captured buffers are kept,
+    not freed)."""
+    import torch
+    from paper_2301_09310_amd import salo
+    small = I.random_pairs(54, 1000, 600, related=0.6)
+    big = I.random_pairs(55, 30000, 300, related=0.6)
+    want_s, want_b = oracle_align(small), oracle_align(big)
+    s = torch.cuda.Stream()
+    q, qo, t, to = salo.to_device(small)
+    out = tuple(torch.empty(small.n_pairs, dtype=torch.int32, device="cuda") for _ in range(3))
+    with torch.cuda.stream(s):
+        salo.reserve(small.n_pairs, stream=s)
+        salo.align_batch(q, qo, t, to, out=out, stream=s)
+    s.synchronize()
+    _say("capture, then grow the workspace with a larger eager call")
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        salo.align_batch(q, qo, t, to, out=out, stream=s)
+    qb, qob, tb, tob = salo.to_device(big)
+    with torch.cuda.stream(s):
+        ob = salo.align_batch(qb, qob, tb, tob, stream=s)
+    s.synchronize()
+    assert_same(big, tuple(x.cpu().numpy().astype(np.int64) for x in ob), want_b, "grown")
+    for rep in range(3):
+        for o in out:
+            o.fill_(-3)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        got = tuple(x.cpu().numpy().astype(np.int64) for x in out)
+        assert_same(small, got, want_s, "replay %d after growth" % rep)

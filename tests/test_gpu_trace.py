@@ -165,3 +165,35 @@ def test_short_reads_full_size_sampled(dev):
     assert np.array_equal(ln[idx], wln)
     for k, p in enumerate(idx):
         assert np.array_equal(cig[off[p]:off[p] + ln[p]], wcig[woff[k]:woff[k] + wln[k]])
+
+
+def test_trace_on_side_stream(dev):
+    """align_trace on a stream other than the current one: the binding's own
+    buffers (offsets, CIGAR arrays, workspace) are made on the launch stream
+    after the current stream's work, and kept from reuse while it runs."""
+    import torch
+    from paper_2301_09310_amd import salo
+    b = I.random_pairs(63, 400, 300, related=0.7)
+    _say("trace on a side stream, pairs", b.n_pairs)
+    q, qo, t, to = salo.to_device(b)
+    ans = salo.align_batch(q, qo, t, to)
+    st = salo.align_starts(q, qo, t, to, ans)
+    side = torch.cuda.Stream()
+    off, cig, ln = salo.align_trace(q, qo, t, to, ans, st, stream=side,
+                                    workspace_bytes=1 << 28)
+    # churn the allocator on the current stream while the side stream runs
+    junk = [torch.empty(1 << 26, dtype=torch.uint8, device=dev).fill_(0xAB) for _ in range(4)]
+    side.synchronize()
+    torch.cuda.synchronize()
+    del junk
+    cpu = lambda x: x.cpu().numpy().astype(np.int64)
+    w_ans = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets)
+    w_st = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *w_ans)
+    woff, wcig, wln = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, w_ans[0],
+                                    w_st[0], w_ans[1], w_st[1], w_ans[2])
+    assert np.array_equal(cpu(off), woff)
+    assert np.array_equal(cpu(ln), wln)
+    g = cig.cpu().numpy().view(np.uint32)
+    for p in np.nonzero(wln > 0)[0]:
+        a, n = woff[p], wln[p]
+        assert np.array_equal(g[a:a + n], wcig[a:a + n]), p
