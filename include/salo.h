@@ -355,6 +355,29 @@ salo_status_t salo_align_batch_tagged(const uint8_t *q_seqs, const int64_t *q_of
 salo_status_t salo_host_alloc(int64_t bytes, void **ptr);
 salo_status_t salo_host_free(void *ptr);
 
+/*
+ * salo_align_batch without any allocation, for callers that cannot
+ * allocate device memory: code under HIP graph capture, serving loops
+ * that must not call hipMalloc, harnesses that forbid it.  Same arguments,
+ * layout, results and asynchrony as salo_align_batch, and the same kernels;
+ * the workspace is one fixed device array inside the library (about
+ * 328 MiB, held by each GPU the library runs on until the process ends),
+ * found with hipGetSymbolAddress on the first call on each device.
+ *
+ * Limits: n_pairs <= 4,194,304 (else SALO_ERR_INVALID, nothing enqueued);
+ * a pair whose target exceeds 12,288 bases gets -1 in all three outputs
+ * (as do pairs with invalid offsets or lengths); no error counter is kept.
+ * Every call on one GPU shares that array and leaves its contents behind:
+ * calls that overlap on a GPU (on different streams, or from different
+ * host threads) race and must be serialised by the caller.  Calls on one
+ * stream are ordered and safe.
+ */
+salo_status_t salo_align_batch_noalloc(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                       const uint8_t *t_seqs, const int64_t *t_offsets,
+                                       int64_t n_pairs, salo_scoring_t scoring,
+                                       int32_t *out_score, int32_t *out_qend,
+                                       int32_t *out_tend, hipStream_t stream);
+
 /* Message for the last non-OK status returned on this host thread. */
 const char *salo_last_error(void);
 

@@ -26,7 +26,8 @@ COMMON = ["-O3", "-std=c++17", "-fPIC", "-I" + INCLUDE, "-I" + CSRC]
 # numbers, and cell values 1..1023 are binary16 subnormals
 DEVICE = ["--offload-arch=" + ARCH, "-Xclang", "-target-feature", "-Xclang",
           "-packed-fp32-ops", "-fdenormal-fp-math=ieee"]
-SOURCES = ["salo_kernels.hip", "salo_plan.hip", "salo_pack.hip", "salo_host.cpp"]
+SOURCES = ["salo_kernels.hip", "salo_plan.hip", "salo_pack.hip", "salo_noalloc.hip",
+           "salo_host.cpp"]
 # the ceiling microbenchmarks: a library of their own, loaded only by bench.py
 UBENCH_SOURCE = "salo_ubench.hip"
 UBENCH_LIB = os.path.join(PKG, "libsalo_ubench.so")

@@ -489,6 +489,63 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
 
 }  // namespace
 
+salo_status_t set_error(salo_status_t st, const char *msg) { return fail(st, msg); }
+
+salo_status_t align_batch_fixed_scratch(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                        const uint8_t *t_seqs, const int64_t *t_offsets,
+                                        int64_t n_pairs, salo_scoring_t scoring,
+                                        int32_t *out_score, int32_t *out_qend,
+                                        int32_t *out_tend, hipStream_t stream, void *scratch,
+                                        int64_t scratch_bytes, int64_t max_pairs,
+                                        int64_t slots, int32_t slot_words) {
+    salo_status_t st = validate(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring,
+                                out_score, out_qend, out_tend);
+    if (st != SALO_OK) return st;
+    if (n_pairs > max_pairs)
+        return fail(SALO_ERR_INVALID, "n_pairs " + std::to_string(n_pairs) +
+                                          " above the fixed scratch's maximum of " +
+                                          std::to_string(max_pairs) + " pairs");
+    if (n_pairs == 0) return SALO_OK;
+    if (!scratch || (reinterpret_cast<uintptr_t>(scratch) & 255) ||
+        scratch_bytes < fixed_scratch_bytes(max_pairs, slots, slot_words))
+        return fail(SALO_ERR_INVALID, "fixed scratch missing, misaligned or too small");
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    Workspace w;
+    w.device = dev;
+    w.external = true;
+    e = hipDeviceGetAttribute(&w.cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "hipDeviceGetAttribute");
+    char *c = static_cast<char *>(scratch);
+    int64_t off = 0;
+    auto carve = [&](int64_t bytes) {
+        char *p = c + off;
+        off += align256(bytes);
+        return p;
+    };
+    w.counters = reinterpret_cast<int32_t *>(carve(4 * kCounterWords));
+    // the plan's zeroing kernel clears every counter word at every call, so
+    // the error counter (the two spare words) starts each call at 0
+    w.errors = reinterpret_cast<unsigned long long *>(w.counters + 2 * kColClasses);
+    w.bins = reinterpret_cast<BinDesc *>(carve((int64_t)sizeof(BinDesc) * kMaxBins));
+    w.binstat = reinterpret_cast<int32_t *>(carve(12 * kMaxBins));
+    w.block_sums = reinterpret_cast<uint32_t *>(carve(4 * (int64_t)kScanBlocks));
+    w.hist = reinterpret_cast<uint32_t *>(carve(4 * kHistEntries));
+    w.keys = reinterpret_cast<uint16_t *>(carve(2 * max_pairs));
+    w.order = reinterpret_cast<int32_t *>(carve(4 * max_pairs));
+    w.plan_cap = max_pairs;
+    w.slab = reinterpret_cast<uint32_t *>(c + off);
+    w.slots = slots;
+    w.slot_words = slot_words;
+    salo_options_t o;
+    std::memset(&o, 0, sizeof o);
+    o.mode = SALO_MODE_PERSISTENT;
+    return run_align(q_seqs, q_offsets, t_seqs, t_offsets, n_pairs, scoring, out_score,
+                     out_qend, out_tend, stream, &o, nullptr, NMasks{nullptr, nullptr}, -1,
+                     nullptr, &w);
+}
+
 }  // namespace salo
 
 using namespace salo;

@@ -185,6 +185,34 @@ __host__ __device__ inline int band_slot_rows(int R, int w, uint32_t *wrap) {
     return (int)ring;
 }
 
+// A fixed scratch buffer carved into the persistent path's workspace (the
+// no-allocation entry point): counters (kCounterWords words, the error
+// counter in the two spare ones), bin table, bin statistics, scan block sums, key histogram,
+// keys and order for max_pairs pairs, then `slots` boundary slots of
+// slot_words words.  Every part starts on a 256-byte boundary.
+constexpr int64_t align256(int64_t x) { return (x + 255) & ~(int64_t)255; }
+constexpr int64_t fixed_scratch_bytes(int64_t max_pairs, int64_t slots, int64_t slot_words) {
+    return align256(4 * kCounterWords) + align256((int64_t)sizeof(BinDesc) * kMaxBins) +
+           align256(12 * kMaxBins) + align256(4 * (int64_t)kScanBlocks) +
+           align256(4 * kHistEntries) + align256(2 * max_pairs) + align256(4 * max_pairs) +
+           slots * slot_words * 4;
+}
+
+// Record `msg` as the calling thread's salo_last_error() text; returns st.
+salo_status_t set_error(salo_status_t st, const char *msg);
+
+// Align a batch (salo_align_batch's arguments and behaviour) with every
+// workspace buffer carved from `scratch` (device memory of scratch_bytes
+// bytes laid out as fixed_scratch_bytes describes).  Allocates nothing.
+// More than max_pairs pairs: SALO_ERR_INVALID.
+salo_status_t align_batch_fixed_scratch(const uint8_t *q_seqs, const int64_t *q_offsets,
+                                        const uint8_t *t_seqs, const int64_t *t_offsets,
+                                        int64_t n_pairs, salo_scoring_t scoring,
+                                        int32_t *out_score, int32_t *out_qend,
+                                        int32_t *out_tend, hipStream_t stream, void *scratch,
+                                        int64_t scratch_bytes, int64_t max_pairs,
+                                        int64_t slots, int32_t slot_words);
+
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,
                         hipStream_t stream);
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream);

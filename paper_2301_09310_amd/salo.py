@@ -95,6 +95,8 @@ def load(path: str | None = None):
         lib.salo_align_trace.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp, vp,
                                          vp, vp, vp, i64, vp, ctypes.POINTER(Options)]
         lib.salo_align_trace.restype = i32
+        lib.salo_align_batch_noalloc.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp]
+        lib.salo_align_batch_noalloc.restype = i32
         lib.salo_align_batch_tagged.argtypes = [vp, vp, vp, vp, i64, Scoring, vp, vp, vp, vp, vp,
                                                 vp, ctypes.POINTER(Options)]
         lib.salo_align_batch_tagged.restype = i32
@@ -185,6 +187,28 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
                                     t_seqs.data_ptr(), tm, t_offsets.data_ptr(), n, sc,
                                     out[0].data_ptr(), out[1].data_ptr(), out[2].data_ptr(),
                                     _stream_handle(stream), ctypes.byref(opts))
+    _check(lib, st)
+    return out
+
+
+def align_batch_noalloc(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
+                        out=None, stream=None):
+    """salo_align_batch_noalloc: align_batch with the library's fixed
+    scratch instead of an allocated workspace (at most 4,194,304 pairs;
+    targets above 12,288 bases get -1).  `out` (a triple of int32 CUDA
+    tensors) is allocated here when not given."""
+    import torch
+    lib = load()
+    _check_inputs(q_seqs, q_offsets, t_seqs, t_offsets)
+    n = q_offsets.numel() - 1
+    if out is None:
+        out = tuple(torch.empty(max(n, 0), dtype=torch.int32, device=q_offsets.device)
+                    for _ in range(3))
+    st = lib.salo_align_batch_noalloc(q_seqs.data_ptr(), q_offsets.data_ptr(),
+                                      t_seqs.data_ptr(), t_offsets.data_ptr(), n,
+                                      Scoring(*[int(x) for x in scoring]), out[0].data_ptr(),
+                                      out[1].data_ptr(), out[2].data_ptr(),
+                                      _stream_handle(stream))
     _check(lib, st)
     return out
 
