@@ -260,6 +260,12 @@ def main(argv=None) -> int:
                     help="most pairs merged into one launch")
     ap.add_argument("--serve-rates", default="0.5,0.8",
                     help="offered loads as fractions of the saturated rate")
+    ap.add_argument("--serve-split", type=int, default=4,
+                    help="split_waves of the served launches (4: long pairs on four waves "
+                         "each; 0: off)")
+    ap.add_argument("--serve-per-launch", action="store_true",
+                    help="complete requests when their whole merged launch ends (no "
+                         "per-request counters)")
     ap.add_argument("--graph", action="store_true", help=argparse.SUPPRESS)
     ap.add_argument("--no-graph", action="store_true",
                     help="time eager calls instead of replays of one captured step (plan + "
@@ -908,14 +914,19 @@ def serve_block(args, pool):
     log("serve: %d requests (%d pairs) carved from the %d-pair pool in %.1fs" % (
         n, int(sizes.sum()), pool.n_pairs, time.time() - t0))
     ex = S.GpuExecutor(n_slots=args.serve_slots, max_pairs=args.serve_launch_pairs,
-                       scoring=SCORING)
+                       scoring=SCORING, per_request=not args.serve_per_launch,
+                       split_waves=args.serve_split)
 
     def run(rate):
         arr = np.zeros(n) if rate is None else S.poisson_arrivals(n, rate, 1)
         reqs = S.with_arrivals(base, arr)
+        k0 = len(ex.launch_split)
         st = S.Server(ex, budget_bytes=budget, progress=log).run(reqs,
                                                                  warmup=args.serve_warmup)
-        return reqs, st.summary()
+        summ = st.summary()
+        ls = ex.launch_split[k0:]
+        summ["split_launches"] = sum(1 for x in ls if x > 1)
+        return reqs, summ
 
     reqs, sat = run(None)              # all requests at once: saturated rate
     log("serve saturated: %s" % json.dumps(sat))
@@ -939,9 +950,13 @@ def serve_block(args, pool):
                               "launches": summ["launches"],
                               "mean_requests_per_launch":
                                   round(summ["mean_requests_per_launch"], 2),
-                              "max_inflight": summ["max_inflight"]}
+                              "max_inflight": summ["max_inflight"],
+                              "split_launches": summ["split_launches"]}
         log("serve %.1fx: %s" % (f, json.dumps(runs["%.1fx" % f])))
     return {"requests": args.serve_requests, "warmup_requests": args.serve_warmup,
+            "completion": "per launch" if args.serve_per_launch else "per request",
+            "split_waves": args.serve_split,
+            "split_rule": "launches with at most 1024 queries above 1024 bases",
             "pairs_per_request": "U{1..4096}", "arrivals": "Poisson (seed 1)",
             "budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
             "launch_pairs": args.serve_launch_pairs,

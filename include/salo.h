@@ -92,14 +92,23 @@ typedef enum {
 typedef struct {
     int32_t mode;           /* salo_mode_t */
     int32_t lanes;          /* lanes per pair group (1,2,4,8,16,32,64); 0 = default */
-    int32_t cols;           /* query columns per lane (8 or 16); 0 = default */
+    int32_t cols;           /* query columns per lane (8, 16 or 32); 0 = default
+                               (each length bin's own, persistent mode) */
     int32_t force_int32;    /* 1: 32-bit cells for every pair */
     int32_t waves_per_cu;   /* grid size in resident waves per CU; 0 = default */
     int32_t timing;         /* 1: record events around the plan and DP kernels
                                (see salo_last_timing); 0 = off */
     int32_t no_f16;         /* 1: never use binary16 cells (16-bit integer or
                                32-bit cells only); results are identical */
-    int32_t reserved;       /* must be 0 */
+    int32_t split_waves;    /* 0 or 1: off.  4: the pairs of the 16-bit bins of
+                               queries above 1024 bases run with 64 lanes and
+                               16 columns per lane, each unit on 4 waves of
+                               one workgroup, one strip of target rows each,
+                               so a long pair finishes sooner (forward pass,
+                               persistent mode; for latency, e.g. serving a
+                               batch with fewer long pairs than the GPU has
+                               SIMDs).  Results are identical.  Other values:
+                               SALO_ERR_INVALID. */
 } salo_options_t;
 
 /* One length bin of the persistent mode: pairs whose query length is at

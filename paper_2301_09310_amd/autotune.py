@@ -12,6 +12,14 @@ K sets the chunk width W*K with W: the padding of a pair's last chunk, how
 often the boundary column is handed over, and the registers per lane
 (K = 32 runs 2 waves per SIMD instead of 3).
 
+The per-bin sweep sees each bin alone.  In a real batch every column class
+is its own persistent launch, and 32 columns per lane run two waves per SIMD
+instead of three, so a second phase confirms each non-default column count
+on whole workloads: starting from every bin at its best width for 16
+columns, it switches one bin at a time to its sweep-best (W, K) and keeps
+the switch only if the reference workloads (a 400,000-pair slice of the
+mixed batch and 1,000,000 short reads) get at least 0.5% faster in total.
+
 Usage (on the GPU):
   python -m paper_2301_09310_amd.autotune --out paper_2301_09310_amd/tune_gfx950.json
 The JSON holds the table and every measurement.  The library's build
@@ -118,6 +126,52 @@ def tune(cells_per_bin: float = 2e10, cols=COLS, seed: int = 7, log=print):
     return result
 
 
+def confirm(bins, seed: int = 0, reps: int = 3, log=print):
+    """Phase two: bins whose sweep-best K is not 16 keep it only if the
+    reference workloads get faster with it (see the module docstring)."""
+    import torch
+    from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import salo
+    refs = [salo.to_device(I.mixed(seed, 400_000)), salo.to_device(I.short_reads(seed, 1_000_000))]
+
+    def total(table):
+        salo.set_bins([(b["m_hi"], b["packed"], b["lanes"], b["cols"]) for b in table])
+        t = 0.0
+        for d in refs:
+            n = d[1].numel() - 1
+            t += time_config(d, n, reps=reps)[0]
+        return t
+
+    base = []
+    for b in bins:
+        k16 = {wk: t for wk, t in b["ms"].items() if wk.endswith("x16")}
+        w16 = min(k16, key=k16.get) if k16 else "%dx16" % b["lanes"]
+        base.append(dict(b, lanes=int(w16.split("x")[0]), cols=16))
+    cur = total(base)
+    log("phase 2: all bins at 16 columns: %.2f ms on the reference workloads" % cur)
+    trials = []
+    for i, b in enumerate(bins):
+        if b["cols"] == 16:
+            continue
+        trial = [dict(x) for x in base]
+        trial[i] = dict(trial[i], lanes=b["lanes"], cols=b["cols"])
+        t = total(trial)
+        keep = t < cur * 0.995
+        log("phase 2: bin m<=%d %s at %dx%d: %.2f ms (%s)" % (
+            b["m_hi"], "16-bit" if b["packed"] else "32-bit", b["lanes"], b["cols"], t,
+            "kept" if keep else "not kept"))
+        trials.append({"m_hi": b["m_hi"], "packed": b["packed"], "lanes": b["lanes"],
+                       "cols": b["cols"], "ms": round(t, 3), "base_ms": round(cur, 3),
+                       "kept": keep})
+        if keep:
+            base, cur = trial, t
+    salo.set_bins(None)
+    for b, s in zip(bins, base):
+        b["sweep_best"] = "%dx%d" % (b["lanes"], b["cols"])
+        b["lanes"], b["cols"] = s["lanes"], s["cols"]
+    return trials
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
     ap.add_argument("--out", default=os.path.join(os.path.dirname(__file__), "tune_gfx950.json"))
@@ -129,12 +183,14 @@ def main(argv=None) -> int:
     from paper_2301_09310_amd import salo
     salo.load()
     t0 = time.time()
-    bins = tune(args.cells_per_bin, cols, log=lambda *a: print(*a, flush=True))
+    say = lambda *a: print(*a, flush=True)
+    bins = tune(args.cells_per_bin, cols, log=say)
+    trials = confirm(bins, log=say)
     props = torch.cuda.get_device_properties(0)
     rec = {"arch": getattr(props, "gcnArchName", "gfx950"), "device": props.name,
            "cus": props.multi_processor_count, "cols_tried": list(cols),
            "date": datetime.date.today().isoformat(), "seconds": round(time.time() - t0, 1),
-           "bins": bins}
+           "bins": bins, "phase2": trials}
     with open(args.out, "w") as f:
         json.dump(rec, f, indent=1)
     print("wrote", args.out, flush=True)

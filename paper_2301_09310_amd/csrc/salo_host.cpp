@@ -334,7 +334,11 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     salo_options_t o;
     std::memset(&o, 0, sizeof o);
     if (opts) o = *opts;
-    if (o.reserved != 0) return fail(SALO_ERR_INVALID, "salo_options_t.reserved must be 0");
+    if (o.split_waves != 0 && o.split_waves != 1 && o.split_waves != 4)
+        return fail(SALO_ERR_INVALID, "split_waves must be 0, 1 or 4");
+    const bool split = o.split_waves == 4;
+    if (split && (starts || band >= 0 || trace || masks.q || masks.t))
+        return fail(SALO_ERR_UNSUPPORTED, "split_waves applies to the forward pass only");
     if (o.no_f16 != 0 && o.no_f16 != 1) return fail(SALO_ERR_INVALID, "no_f16 must be 0 or 1");
     if (o.mode < SALO_MODE_AUTO || o.mode > SALO_MODE_PERSISTENT)
         return fail(SALO_ERR_INVALID, "unknown mode");
@@ -469,15 +473,35 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
               : make_bin_table(cols, o.lanes ? o.lanes
                                              : (band >= 0 ? band_lanes(band, cols, n_pairs, grid)
                                                           : 0));
-    p.n_bins = bt.n_bins;
+    // the split class takes the 16-bit bins of queries above 1024 bases,
+    // in the split kernel's shape (64 lanes, 16 columns per lane)
+    BinTable btx = bt;
+    bool any_split = false;
+    for (int b = 0; b < btx.n_bins; ++b) {
+        btx.split[b] = split && btx.packed[b] && btx.m_lo[b] >= 1024 ? 1 : 0;
+        if (btx.split[b]) {
+            btx.lanes[b] = 64;
+            btx.cols[b] = 16;
+        }
+        any_split = any_split || btx.split[b];
+    }
+    p.n_bins = btx.n_bins;
     PlanBuffers pb{ws->keys, ws->order, ws->hist, ws->block_sums, ws->binstat};
-    hipError_t e = launch_plan(p, bt, pb, stream);
+    hipError_t e = launch_plan(p, btx, pb, stream);
     if (e != hipSuccess) return hip_fail(e, "launch plan kernels");
     p.order = ws->order;
     if ((st = mark(1)) != SALO_OK) return st;
-    // one launch per column class that a bin uses, widest first
-    bool used[kColClasses] = {false, false, false};
-    for (int b = 0; b < bt.n_bins; ++b) used[col_class(bt.cols[b])] = true;
+    // the split class first (its units are the longest), then one launch
+    // per column class that a bin uses, widest first
+    if (any_split) {
+        // two resident 4-wave workgroups per CU (8 of the slots' waves)
+        const int64_t g = std::min<int64_t>(grid, (int64_t)ws->cus * 8) / 4;
+        e = launch_split(p, 16, 4, (int)g, stream);
+        if (e != hipSuccess) return hip_fail(e, "launch split kernel");
+    }
+    bool used[kColClasses] = {false, false, false, false};
+    for (int b = 0; b < btx.n_bins; ++b)
+        if (!btx.split[b]) used[col_class(btx.cols[b])] = true;
     for (int k : {32, 16, 8}) {
         if (!used[col_class(k)]) continue;
         const int64_t g = std::min<int64_t>(grid, (int64_t)ws->cus * wpc_of(k));

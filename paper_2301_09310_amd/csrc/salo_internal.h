@@ -30,16 +30,23 @@ struct BinDesc {
     int32_t units;        // units of this bin            (device-written)
     int32_t unit0;        // first global unit index      (device-written)
     int32_t n_min, n_max; // target length range          (device-written)
+    int32_t split;        // 1: the split class runs this bin's units
 };
 
 // Query columns per lane (K) of a bin select one of three kernel
 // instantiations; units are numbered within each such column class, and one
-// persistent launch per class claims that class's units.
-constexpr int kColClasses = 3;
+// persistent launch per class claims that class's units.  A fourth class,
+// the split class, holds the bins whose units run on several waves each
+// (salo_options_t.split_waves).
+constexpr int kColClasses = 4;
+constexpr int kSplitClass = 3;
 __host__ __device__ inline int col_class(int cols) { return cols == 8 ? 0 : cols == 16 ? 1 : 2; }
+__host__ __device__ inline int bin_class(int cols, int split) {
+    return split ? kSplitClass : col_class(cols);
+}
 // unit counters [0, kColClasses), unit totals [kColClasses, 2 kColClasses),
 // then two spare words (the fixed scratch's error counter)
-constexpr int kCounterWords = 8;
+constexpr int kCounterWords = 2 * kColClasses + 2;
 
 // Static description of the bins, passed by value to the plan kernels.
 struct BinTable {
@@ -49,6 +56,7 @@ struct BinTable {
     int32_t packed[kMaxBins];  // 1: 16-bit bin, 0: 32-bit bin
     int32_t lanes[kMaxBins];
     int32_t cols[kMaxBins];
+    int32_t split[kMaxBins];   // 1: units run by the split class (several waves each)
 };
 
 // Sort keys: bin (4 bits) | chunk count above the bin's minimum (4 bits,
@@ -216,6 +224,8 @@ salo_status_t align_batch_fixed_scratch(const uint8_t *q_seqs, const int64_t *q_
 hipError_t launch_plain(const KParams &p, int lanes, int cols, int grid,
                         hipStream_t stream);
 hipError_t launch_persistent(const KParams &p, int cols, int grid, hipStream_t stream);
+// the split class: workgroups of `waves` waves (4), 16 columns per lane
+hipError_t launch_split(const KParams &p, int cols, int waves, int grid, hipStream_t stream);
 hipError_t launch_pack(const uint8_t *chars, int64_t n_chars, const int64_t *offsets,
                        int64_t n_seqs, bool revcomp, uint8_t *packed, uint32_t *n_mask,
                        unsigned long long *invalid, hipStream_t stream);

@@ -496,6 +496,43 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
 // integers or as binary16 numbers.
 enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
 
+// Strip split: one unit (a 64-lane group holding one or two long pairs) on
+// several waves of a workgroup, for latency.  The target rows are cut into
+// nw strips; wave ws runs every chunk of strip ws, in chunk order.  Chunk c
+// of strip ws starts from the bottom row of chunk c of strip ws - 1 (H of
+// its last row and F of the row after, per column: 2K words per lane),
+// which that strip's wave stores when it finishes the chunk, into a ring
+// of kSplitRing entries in its global slot; per-strip counters in LDS say
+// how many chunks each strip has produced and taken.  A strip waits only
+// for the strip above to produce and the strip below to take: the last
+// strip never waits to produce and the first never waits for input, so
+// every wait ends (each wait is also bounded: after kSpinLimit polls the
+// unit is flagged and its pairs get -1).
+constexpr int kSplitRing = 4;
+constexpr int kSpinLimit = 1 << 22;
+struct SplitCtx {
+    int nw, ws;            // strips of the unit, this wave's strip
+    int r_lo, r_hi;        // this strip's target rows
+    uint32_t *ring;        // this wave's top-row ring (global, 2K words per lane per entry)
+    uint32_t *ring_above;  // the ring of strip ws - 1
+    int32_t *prod, *cons;  // LDS [nw]: chunks produced / taken by each strip
+    int32_t *fail;         // LDS: set when a wait gave up
+    unsigned long long *keys;  // LDS [nw][2]: each strip's best per pair
+};
+__device__ __forceinline__ bool wait_at_least(int32_t *p, int32_t v, int32_t *fail) {
+    for (int it = 0; it < kSpinLimit; ++it) {
+        const int32_t x = __builtin_amdgcn_readfirstlane(
+            __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_WORKGROUP));
+        if (x >= v) return true;
+        if (__builtin_amdgcn_readfirstlane(
+                __hip_atomic_load(fail, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP)))
+            return false;
+        __builtin_amdgcn_s_sleep(2);
+    }
+    __hip_atomic_store(fail, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return false;
+}
+
 // One unit: G = 64/W groups; each group aligns NPG pairs (2 packed, 1 wide).
 // pos0: first position (in processing order) of the unit's pairs.
 // [g0, g0 + gn): the groups processed in this pass (all G normally; fewer
@@ -511,11 +548,12 @@ enum CellType : int { kCellWide = 0, kCellU16 = 1, kCellF16 = 2 };
 // of (below) the band only ever sees the boundary's E (F), and one right
 // of (above) it only feeds other out-of-band cells -- with H = 0 the
 // in-band cells see exactly the boundary values of the restricted table.
-template <int K, int CT, bool REV, bool NM, bool BAND, bool TR>
+template <int K, int CT, bool REV, bool NM, bool BAND, bool TR, bool SPL = false>
 __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseStream ts,
                                          BaseStream qm, BaseStream tm,
                          int64_t pos0, int64_t pos_end, int g0, int gn, int W,
-                         uint32_t *slot, uint32_t *lds_saved, uint32_t *lds_bnd) {
+                         uint32_t *slot, uint32_t *lds_saved, uint32_t *lds_bnd,
+                         const SplitCtx *sp = nullptr) {
     const int G = kWave / W;
     constexpr bool PK = CT != kCellWide;
     constexpr int NPG = PK ? 2 : 1;
@@ -523,6 +561,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     static_assert(!(BAND && (REV || NM)), "the banded pass is forward, without N masks");
     static_assert(!TR || (CT != kCellF16 && !REV && !NM && !BAND),
                   "the trace pass runs integer cells, forward, without masks or band");
+    static_assert(!SPL || (CT != kCellWide && !REV && !NM && !BAND && !TR),
+                  "the strip split runs the forward pass in 16-bit cells");
     const int lane = threadIdx.x & (kWave - 1);
     const int g = lane / W;          // W is a power of two
     const int l = lane & (W - 1);
@@ -580,7 +620,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         (uint32_t)__builtin_bit_cast(uint16_t, (_Float16)(float)(-beta)) * 0x10001u;
 
     uint32_t *my_saved = lds_saved + (size_t)lane * (2 * K);
-    const Slot bslot{slot, (uint32_t)P.slot_words * 4u};
+    // (strip split: the column in the slot's lower half, the top-row ring in
+    // its upper half)
+    const Slot bslot{slot, (uint32_t)P.slot_words * (SPL ? 2u : 4u)};
     // trace pass: this group's share of the block's code slot; the pair's
     // codes take (its chunks) x n rows x W lanes x K/2 bytes, laid out
     // [chunk][row][lane] so that the group's stores of one step are
@@ -609,10 +651,18 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     // at most 64 groups keep every offset in 32 bits)
     const uint32_t row_bytes = (uint32_t)Gs * 8u;
     const uint32_t ld_lane = (uint32_t)gs * 8u;
+    // strip split: this wave's target rows [v_lo, v_lo + rows); rows outside
+    // them (and past each pair's end) get the zero substitution table
+    const int v_lo = SPL ? sp->r_lo : 0;
+    const int Rc = SPL ? sp->r_hi - sp->r_lo : R;     // rows of the boundary column
+    int lim[NPG];
+#pragma unroll
+    for (int h = 0; h < NPG; ++h)
+        lim[h] = SPL ? max(0, min(pr[h].n, sp->r_hi) - v_lo) : pr[h].n;
     // unbanded: the column in LDS, resident when the whole column fits, else
     // through the rings (Gs is then a power of two, so a 1 KiB block holds
     // SB = 128 / Gs whole rows)
-    const bool bnd_res = (uint32_t)R * row_bytes <= kBndLdsBytes;
+    const bool bnd_res = (uint32_t)Rc * row_bytes <= kBndLdsBytes;
     const uint32_t bnd_mask = bnd_res ? 0xFFFFFFFFu : 2u * kBndBlockBytes - 1u;
     const uint32_t bnd_wbase = bnd_res ? 0u : 2u * kBndBlockBytes;
     const int sb_shift = __builtin_ctz(kBndBlockBytes / row_bytes);
@@ -623,8 +673,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         const int c0 = c * W * K;
         // rows of this chunk: r0 .. r0 + nrows - 1 (all rows unbanded);
         // step s runs row r0 + s - l on lane l
-        const int r0 = BAND ? max(0, c0 - bw) : 0;
-        const int nrows = BAND ? min(R - 1, c0 + W * K - 1 + bw) - r0 + 1 : R;
+        const int r0 = BAND ? max(0, c0 - bw) : v_lo;
+        const int nrows = BAND ? min(R - 1, c0 + W * K - 1 + bw) - r0 + 1 : Rc;
         // last row the previous chunk wrote to the slot
         const int bnd_hi = BAND ? min(R - 1, c0 - 1 + bw) : R - 1;
         auto slot_off = [&](int row) -> uint32_t {
@@ -735,11 +785,47 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         int32_t crow[NPG];
 #pragma unroll
         for (int h = 0; h < NPG; ++h) crow[h] = -1;
+        // 16-bit cells: which of the lane's two row buffers holds each pair's
+        // saved row; a row where both pairs improve is saved once for both
+        int sbA = 0, sbB = 1;
 
         const bool have_bnd = c > 0;   // implies R >= 1 (C == 0 when R == 0)
         const bool write_bnd = c + 1 < C;
         const bool first_lane = l == 0;
         const bool last_lane = l == W - 1 && mine;
+        constexpr int kRowWords = kWave * 2 * K;   // one ring entry: 2K words per lane
+        if constexpr (SPL) {
+            // this chunk's bottom row goes to ring entry c mod kSplitRing:
+            // wait until the strip below has taken the chunk that used it
+            if (sp->ws + 1 < sp->nw && c >= kSplitRing)
+                (void)wait_at_least(sp->cons + sp->ws + 1, c - kSplitRing + 1, sp->fail);
+            if (sp->ws > 0) {
+                // start from this chunk's bottom row in the strip above: H of
+                // row r_lo - 1 and F of row r_lo per column; lane 0's diagonal
+                // is H of row r_lo - 1 in the previous chunk's last column
+                if (wait_at_least(sp->prod + sp->ws - 1, c + 1, sp->fail)) {
+                    const uint32_t *e = sp->ring_above + (size_t)(c % kSplitRing) * kRowWords +
+                                        (size_t)lane * (2 * K);
+#pragma unroll
+                    for (int k = 0; k < K; k += 4) {
+                        const uint4 hv = *reinterpret_cast<const uint4 *>(e + k);
+                        const uint4 fv = *reinterpret_cast<const uint4 *>(e + K + k);
+                        H[k] = hv.x; H[k + 1] = hv.y; H[k + 2] = hv.z; H[k + 3] = hv.w;
+                        F[k] = fv.x; F[k + 1] = fv.y; F[k + 2] = fv.z; F[k + 3] = fv.w;
+                    }
+                    const uint32_t d0 =
+                        c > 0 ? sp->ring_above[(size_t)((c - 1) % kSplitRing) * kRowWords +
+                                               (size_t)(kWave - 1) * (2 * K) + (K - 1)]
+                              : 0u;
+                    hprev = shift_in(H[K - 1], d0, first_lane);
+                    // the entry may be reused once these loads are done
+                    asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                }
+                if (lane == 0)
+                    __hip_atomic_store(sp->cons + sp->ws, c + 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+            }
+        }
         // banded: the boundary rows of the next four steps, in flight
         uint2 fifo[BAND ? 4 : 1];
         // unbanded: the boundary row of the current step (read one step
@@ -805,7 +891,13 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             if constexpr (NM) tn_nx[h] = target_n_bits(h, 0);
         }
         // steps s0 .. s0+3 for s0 = sa, sa+4, ... < sb (sa a multiple of 4)
-        auto run_steps = [&](int sa, int sb, auto masked) {
+        // `frozen` (compile time): strip split, the first W - 1 steps of a
+        // strip below the first, where lane l has no row before step l and
+        // keeps its starting state
+        // `bulk` (compile time, unbanded): every step of the range has
+        // s >= W - 1 and s + 1 < Rc, so the step-range checks of the
+        // boundary reader and writer are left out
+        auto run_steps = [&](int sa, int sb, auto masked, auto frozen, auto bulk) {
         for (int s0 = sa; s0 < sb; s0 += 4) {
             if ((s0 & 15) == 0) {
                 // the next 16 target bases of each pair, already in flight;
@@ -827,10 +919,12 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             // four steps; `masked` (compile time) applies the band mask
             auto steps4 = [&](auto masked) {
             constexpr bool MASK = BAND && decltype(masked)::value;
+            constexpr bool FROZEN = SPL && decltype(frozen)::value;
+            constexpr bool BULK = !BAND && decltype(bulk)::value;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int s = s0 + j;
-                if (s < S) {
+                if (BULK || s < S) {
                 const int i = r0 + s - l;
                 uint2 bnd;
                 if constexpr (BAND) {
@@ -839,21 +933,14 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 } else {
                     bnd = bnd_cur;
                     if (have_bnd) {
-                        // row rn = s + 1 for the next step; when rn starts
-                        // block kb, block kb + 1 (in flight) goes into the
-                        // read ring in place of block kb - 1, and kb + 2 is
-                        // loaded (rows past the column read as 0)
+                        // row rn = s + 1 for the next step (rows past the
+                        // column read as 0); in ring mode its block is in
+                        // the read ring (see the block events below)
                         const int rn = s + 1;
-                        if (!bnd_res && (rn & ((1 << sb_shift) - 1)) == 0) {
-                            const uint32_t kb = (uint32_t)rn >> sb_shift;
-                            lds_store16(lds_bnd, ((kb + 1u) & 1u) * kBndBlockBytes + lane16,
-                                        inflight);
-                            asm volatile("" ::: "memory");
-                            inflight = bslot.load16((kb + 2u) * kBndBlockBytes + lane16);
-                        }
-                        bnd_cur = rn < R ? lds_load8(lds_bnd, (((uint32_t)rn * row_bytes) &
-                                                               bnd_mask) + ld_lane)
-                                         : make_uint2(0u, 0u);
+                        bnd_cur = (BULK || rn < Rc)
+                                      ? lds_load8(lds_bnd, (((uint32_t)rn * row_bytes) & bnd_mask) +
+                                                               ld_lane)
+                                      : make_uint2(0u, 0u);
                     }
                 }
                 // banded: bit k set when column col0 + k of row i is in the band
@@ -867,6 +954,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 auto inband = [&](int k) -> uint32_t {
                     return MASK ? (uint32_t)((int32_t)(bmask << (31 - k)) >> 31) : 0xFFFFFFFFu;
                 };
+                if (!FROZEN || l <= s) {
                 const uint32_t hin = shift_in(hout, bnd.x, first_lane);
                 const uint32_t ein = shift_in(eout, bnd.y, first_lane);
                 // every lane runs every step: rows outside [0, n) of a pair
@@ -884,9 +972,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
                     const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
                     const uint32_t TA =
-                        (uint32_t)i < (uint32_t)pr[0].n ? (MM4 ^ (XM << (bA << 3))) : 0u;
+                        (uint32_t)(i - v_lo) < (uint32_t)lim[0] ? (MM4 ^ (XM << (bA << 3))) : 0u;
                     const uint32_t TB =
-                        (uint32_t)i < (uint32_t)pr[1].n ? (MM4 ^ (XM << (bB << 3))) : 0u;
+                        (uint32_t)(i - v_lo) < (uint32_t)lim[1] ? (MM4 ^ (XM << (bB << 3))) : 0u;
                     // the diagonal term of column k+1 is formed in column
                     // k's step, from H[k] before it takes row i: it is
                     // independent of the E chain (hh, ha, e), so it fills
@@ -913,8 +1001,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
                     // rows past the pair's end (and N rows) get the zero
                     // table: a mismatch in every column
-                    bool okA = (uint32_t)i < (uint32_t)pr[0].n;
-                    bool okB = (uint32_t)i < (uint32_t)pr[1].n;
+                    bool okA = (uint32_t)(i - v_lo) < (uint32_t)lim[0];
+                    bool okB = (uint32_t)(i - v_lo) < (uint32_t)lim[1];
                     if constexpr (NM) {
                         okA = okA && !((tn[0] >> ((s0 & 15) + j)) & 1u);
                         okB = okB && !((tn[1] >> ((s0 & 15) + j)) & 1u);
@@ -983,7 +1071,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         }
                     }
                 } else {
-                    bool okt = (uint32_t)i < (uint32_t)pr[0].n;
+                    bool okt = (uint32_t)(i - v_lo) < (uint32_t)lim[0];
                     if constexpr (NM) okt = okt && !((tn[0] >> ((s0 & 15) + j)) & 1u);
                     // 4 never equals a query code (0..3, or 5 past the end / N)
                     const uint32_t tb = okt ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
@@ -1041,26 +1129,46 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 hprev = hin;
                 hout = H[K - 1];
                 eout = e;
+                if constexpr (SPL) {
+                    // the strip's last row: the next strip starts from it
+                    if (i == sp->r_hi - 1 && sp->ws + 1 < sp->nw) {
+                        uint32_t *e2 = sp->ring + (size_t)(c % kSplitRing) * kRowWords +
+                                       (size_t)lane * (2 * K);
+#pragma unroll
+                        for (int k = 0; k < K; k += 4) {
+                            *reinterpret_cast<uint4 *>(e2 + k) =
+                                make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                            *reinterpret_cast<uint4 *>(e2 + K + k) =
+                                make_uint4(F[k], F[k + 1], F[k + 2], F[k + 3]);
+                        }
+                    }
+                }
                 // row-level tracking of the first maximum
                 if constexpr (PK) {
                     const uint32_t nb = pmax(cbest, rowmax);
                     const uint32_t chg = nb ^ cbest;
                     cbest = nb;
                     if (chg != 0u) {
-                        if (chg & 0xFFFFu) {
+                        // one save per row: both pairs improving share a
+                        // buffer; one pair alone takes a buffer the other
+                        // pair's saved row is not in
+                        const bool cA = (chg & 0xFFFFu) != 0u, cB = (chg >> 16) != 0u;
+                        const int x = (cA && cB) ? 0
+                                      : cA ? (sbA == sbB ? 1 - sbB : sbA)
+                                           : (sbA == sbB ? 1 - sbA : sbB);
+                        if (cA) {
                             crow[0] = i;
-#pragma unroll
-                            for (int k = 0; k < K; k += 4)
-                                *reinterpret_cast<uint4 *>(my_saved + k) =
-                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                            sbA = x;
                         }
-                        if (chg >> 16) {
+                        if (cB) {
                             crow[1] = i;
-#pragma unroll
-                            for (int k = 0; k < K; k += 4)
-                                *reinterpret_cast<uint4 *>(my_saved + K + k) =
-                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                            sbB = x;
                         }
+                        uint32_t *dst = my_saved + x * K;
+#pragma unroll
+                        for (int k = 0; k < K; k += 4)
+                            *reinterpret_cast<uint4 *>(dst + k) =
+                                make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
                     }
                 } else {
                     if ((int)rowmax > (int)cbest) {
@@ -1072,6 +1180,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                                 make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
                     }
                 }
+                }  // live lane
                 // the group's last lane holds row r0 + s - (W-1): one of the
                 // chunk's rows once s >= W-1 (and never past them, as
                 // s < nrows + W - 1)
@@ -1079,22 +1188,44 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     if (write_bnd && s >= W - 1 && last_lane)
                         bslot.store(ld_lane + ((uint32_t)(r0 + s - (W - 1)) & rwrap) * row_bytes,
                                     hout, eout);
-                } else if (write_bnd && s >= W - 1) {
+                } else if (write_bnd && (BULK || s >= W - 1)) {
                     // row r of this chunk's column into LDS; in ring mode a
                     // completed block goes to the slot as one burst
                     const uint32_t r = (uint32_t)(s - (W - 1));
                     if (last_lane)
                         lds_store8(lds_bnd, bnd_wbase + ((r * row_bytes) & bnd_mask) + ld_lane,
                                    hout, eout);
-                    if (!bnd_res && ((r + 1u) & ((1u << sb_shift) - 1u)) == 0) {
-                        asm volatile("" ::: "memory");
-                        const uint32_t kb = r >> sb_shift;
-                        const uint4 v = lds_load16(lds_bnd, bnd_wbase + (kb & 1u) * kBndBlockBytes +
-                                                               lane16);
-                        bslot.store16(kb * kBndBlockBytes + lane16, v);
-                    }
                 }
                 }  // s < S
+            }
+            if constexpr (!BAND) {
+                // ring events of this block of four steps (a ring block
+                // holds at least 4 rows, so at most one of each happens):
+                //  * the rows written here completed block kw: the wave
+                //    copies it to the slot as one burst;
+                //  * the rows read here entered block kr: block kr + 1 (in
+                //    flight) goes into the read ring in place of kr - 1,
+                //    and kr + 2 is loaded (past the column it reads stale
+                //    slot words or zeros; such rows are never used)
+                if (!bnd_res) {
+                    const int sh = sb_shift;
+                    const int rw_hi = min(s0 + 3 - (W - 1), Rc - 1);
+                    const int rw_lo = max(s0 - (W - 1), 0);
+                    if (write_bnd && rw_hi >= rw_lo && ((rw_hi + 1) >> sh) > (rw_lo >> sh)) {
+                        const uint32_t kw = (uint32_t)(((rw_hi + 1) >> sh) - 1);
+                        asm volatile("" ::: "memory");
+                        const uint4 v = lds_load16(lds_bnd, bnd_wbase +
+                                                                (kw & 1u) * kBndBlockBytes + lane16);
+                        bslot.store16(kw * kBndBlockBytes + lane16, v);
+                    }
+                    if (have_bnd && ((s0 + 4) >> sh) > (s0 >> sh)) {
+                        const uint32_t kr = (uint32_t)((s0 + 4) >> sh);
+                        lds_store16(lds_bnd, ((kr + 1u) & 1u) * kBndBlockBytes + lane16,
+                                    inflight);
+                        asm volatile("" ::: "memory");
+                        inflight = bslot.load16((kr + 2u) * kBndBlockBytes + lane16);
+                    }
+                }
             }
             };
             steps4(masked);
@@ -1106,18 +1237,45 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             // inside that range skip the mask
             const int a = min(max(0, (s_lo + 3) & ~3), (S + 3) & ~3);
             const int b = max(a, min(((s_hi + 1) & ~3), (S + 3) & ~3));
-            run_steps(0, a, std::true_type{});
-            run_steps(a, b, std::false_type{});
-            run_steps(b, S, std::true_type{});
+            run_steps(0, a, std::true_type{}, std::false_type{}, std::false_type{});
+            run_steps(a, b, std::false_type{}, std::false_type{}, std::false_type{});
+            run_steps(b, S, std::true_type{}, std::false_type{}, std::false_type{});
         } else {
-            run_steps(0, S, std::false_type{});
+            // head (the wavefront's ramp: lanes before their first row; a
+            // strip below the first keeps them frozen), bulk, tail (rows
+            // past the column); the N-mask and trace kernels, which hold
+            // more registers, keep one loop with the checks in every step
+            const int a = min((W - 1 + 3) & ~3, (S + 3) & ~3);
+            const int b = max(a, (Rc - 1) & ~3);
+            if (SPL && sp->ws > 0) {
+                run_steps(0, a, std::false_type{}, std::true_type{}, std::false_type{});
+                run_steps(a, b, std::false_type{}, std::false_type{}, std::true_type{});
+                run_steps(b, S, std::false_type{}, std::false_type{}, std::false_type{});
+            } else if constexpr (!NM && !TR) {
+                run_steps(0, a, std::false_type{}, std::false_type{}, std::false_type{});
+                run_steps(a, b, std::false_type{}, std::false_type{}, std::true_type{});
+                run_steps(b, S, std::false_type{}, std::false_type{}, std::false_type{});
+            } else {
+                run_steps(0, S, std::false_type{}, std::false_type{}, std::false_type{});
+            }
+        }
+        if constexpr (!BAND) {
             // ring mode: the column's last, partial block goes to the slot
-            if (write_bnd && !bnd_res && ((uint32_t)R & ((1u << sb_shift) - 1u)) != 0) {
+            if (write_bnd && !bnd_res && ((uint32_t)Rc & ((1u << sb_shift) - 1u)) != 0) {
                 asm volatile("" ::: "memory");
-                const uint32_t kb = (uint32_t)R >> sb_shift;
+                const uint32_t kb = (uint32_t)Rc >> sb_shift;
                 const uint4 v =
                     lds_load16(lds_bnd, bnd_wbase + (kb & 1u) * kBndBlockBytes + lane16);
                 bslot.store16(kb * kBndBlockBytes + lane16, v);
+            }
+        }
+        if constexpr (SPL) {
+            // this chunk's bottom row is stored: the strip below may start it
+            if (sp->ws + 1 < sp->nw) {
+                asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+                if (lane == 0)
+                    __hip_atomic_store(sp->prod + sp->ws, c + 1, __ATOMIC_RELEASE,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
             }
         }
 
@@ -1129,8 +1287,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 int kk = K - 1;
 #pragma unroll
                 for (int k = K - 1; k >= 0; --k) {
-                    const uint32_t hv = PK ? ((my_saved[h * K + k] >> (16 * h)) & 0xFFFFu)
-                                           : my_saved[k];
+                    const uint32_t hv =
+                        PK ? ((my_saved[(h ? sbB : sbA) * K + k] >> (16 * h)) & 0xFFFFu)
+                           : my_saved[k];
                     if (hv == v) kk = k;
                 }
                 best[h].offer(CT == kCellF16 ? half_bits_to_int(v) : (int32_t)v, crow[h],
@@ -1151,6 +1310,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             // pairs of a one-lane group)
             if (mine && l == (W > 1 ? h : 0))
                 trace_walk<K, PK>(P, pr[h], key, tr_codes, tr_fits, W, h, tr_rows, qs, ts);
+        } else if constexpr (SPL) {
+            // the strips' bests merge in the workgroup (split_kernel)
+            if (lane == 0) sp->keys[sp->ws * 2 + h] = key;
         } else {
             if (l == 0 && mine) {
                 write_result<REV>(P, pr[h], key);
@@ -1201,8 +1363,14 @@ __device__ __forceinline__ void process_unit(const KParams &P, BaseStream qs, Ba
     // instantiation keeps run_unit inlined.
     int fit = (int)min<int64_t>(G, (int64_t)P.slot_words / (2 * (int64_t)max(rows, 1)));
     // unbanded passes keep a power-of-two group count (the LDS ring's
-    // blocks hold whole rows); G is a power of two, so every pass is full
-    if (!BAND) fit = 1 << (31 - __builtin_clz((unsigned)fit));
+    // blocks hold whole rows); G is a power of two, so every pass is full.
+    // A column that leaves LDS goes through 1 KiB ring blocks of at least
+    // 4 rows, so at most 32 groups share it (1-lane groups then run in two
+    // passes)
+    if (!BAND) {
+        fit = 1 << (31 - __builtin_clz((unsigned)fit));
+        if (fit > 32 && (int64_t)rows * fit * 8 > (int64_t)kBndLdsBytes) fit = 32;
+    }
     const int passes = (G + fit - 1) / fit;
     // with N masks the host turns binary16 cells off (their table cannot
     // give an N column the mismatch), so NM never instantiates them
@@ -1311,7 +1479,7 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
         int b = 0;
         for (int k = 0; k < kMaxBins; ++k) {
             const int u0 = P.bins[k].unit0, nu = P.bins[k].units;
-            if (P.bins[k].cols == K && u >= u0 && u < u0 + nu) b = k;
+            if (!P.bins[k].split && P.bins[k].cols == K && u >= u0 && u < u0 + nu) b = k;
         }
         b = __builtin_amdgcn_readfirstlane(b);
         const BinDesc &bd = P.bins[b];
@@ -1323,6 +1491,112 @@ __global__ __launch_bounds__(64) __attribute__((amdgpu_waves_per_eu(kMinWaves<K,
         const int np = (int)min<int64_t>(ppu, first + count - pos0);
         process_unit<K, REV, NM, BAND, TR>(P, qs, ts, qm, tm, pos0, np, lanes, slot, lds_saved,
                                            lds_bnd);
+    }
+}
+
+// A strip needs at least this many rows to be worth a wave of its own.
+constexpr int kMinStripRows = 256;
+
+// The split class (calls with split_waves set): units of 64-lane bins, each
+// run by NW waves of one workgroup, one strip of target rows per wave (the
+// protocol is at SplitCtx).  A workgroup claims units from the class's
+// counter; a unit with too few rows, or with 32-bit cells, runs on the
+// workgroup's first wave alone.  The strips' bests merge into the first
+// maximum over the whole table (the strips are row ranges in order, and
+// the 64-bit keys order by score, then first row, then first column).
+// (two resident waves per SIMD: the kernel holds the split and the
+// single-wave unit code, and needs more than three waves' share of
+// registers without spilling)
+template <int K, int NW>
+__global__ __launch_bounds__(kWave * NW) __attribute__((amdgpu_waves_per_eu(2, 8))) void split_kernel(KParams P) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds_saved[NW][kWave * 2 * K];
+    __shared__ __attribute__((aligned(16))) uint32_t lds_bnd[NW][kBndLdsBytes / 4];
+    __shared__ int32_t s_prod[NW], s_cons[NW];
+    __shared__ int32_t s_fail, s_unit;
+    __shared__ unsigned long long s_keys[2 * NW];
+    const int wv = __builtin_amdgcn_readfirstlane((int)(threadIdx.x / kWave));
+    const int lane = threadIdx.x & (kWave - 1);
+    BaseStream qs, ts, qm, tm;
+    qs.init(P.q_seqs, P.q_off, P.n_pairs);
+    ts.init(P.t_seqs, P.t_off, P.n_pairs);
+    qm.init_mask(nullptr, P.q_off, P.n_pairs);
+    tm.init_mask(nullptr, P.t_off, P.n_pairs);
+    const size_t sw = (size_t)P.slot_words;
+    uint32_t *slot = P.scratch + ((size_t)blockIdx.x * NW + wv) * sw;
+    int32_t *const counter = P.unit_counter + kSplitClass;
+    const int total = __builtin_amdgcn_readfirstlane(P.total_units[kSplitClass]);
+    for (;;) {
+        if (threadIdx.x == 0) {
+            s_unit = atomicAdd(counter, 1);
+            s_fail = 0;
+        }
+        if (threadIdx.x < NW) {
+            s_prod[threadIdx.x] = 0;
+            s_cons[threadIdx.x] = 0;
+        }
+        if (threadIdx.x < 2 * NW) s_keys[threadIdx.x] = 0ull;
+        __syncthreads();
+        const int u = __builtin_amdgcn_readfirstlane(s_unit);
+        if (u >= total) break;
+        int b = 0;
+        for (int k = 0; k < kMaxBins; ++k) {
+            const int u0 = P.bins[k].unit0, nu = P.bins[k].units;
+            if (P.bins[k].split && u >= u0 && u < u0 + nu) b = k;
+        }
+        b = __builtin_amdgcn_readfirstlane(b);
+        const BinDesc &bd = P.bins[b];
+        const int lanes = __builtin_amdgcn_readfirstlane(bd.lanes);
+        const int ppu = __builtin_amdgcn_readfirstlane(bd.pairs);
+        const int64_t first = __builtin_amdgcn_readfirstlane(bd.first);
+        const int64_t count = __builtin_amdgcn_readfirstlane(bd.count);
+        const int64_t pos0 =
+            first + (int64_t)(u - __builtin_amdgcn_readfirstlane(bd.unit0)) * ppu;
+        const int np = (int)min<int64_t>(ppu, first + count - pos0);
+        // the unit's rows and cell type (the same in every wave)
+        int rmax = 0;
+        for (int k = lane; k < np; k += kWave)
+            rmax = max(rmax, load_pair<false>(P, pos0 + k, pos0 + np, true).n);
+        const int R = wave_max(rmax);
+        const int ct = unit_cell_type<false>(P, pos0, np);
+        const int nw = (ct == kCellWide || lanes != kWave) ? 1
+                                                           : min(NW, max(1, R / kMinStripRows));
+        if (nw == 1) {
+            if (wv == 0)
+                process_unit<K, false, false, false, false>(P, qs, ts, qm, tm, pos0, np, lanes,
+                                                            slot, lds_saved[0], lds_bnd[0]);
+        } else if (wv < nw) {
+            const int rs = (R + nw - 1) / nw;
+            SplitCtx sp;
+            sp.nw = nw;
+            sp.ws = wv;
+            sp.r_lo = wv * rs;
+            sp.r_hi = min(R, (wv + 1) * rs);
+            sp.ring = slot + sw / 2;
+            sp.ring_above =
+                wv > 0 ? P.scratch + ((size_t)blockIdx.x * NW + wv - 1) * sw + sw / 2 : nullptr;
+            sp.prod = s_prod;
+            sp.cons = s_cons;
+            sp.fail = &s_fail;
+            sp.keys = s_keys;
+            if (ct == kCellF16)
+                run_unit<K, kCellF16, false, false, false, false, true>(
+                    P, qs, ts, qm, tm, pos0, pos0 + np, 0, 1, kWave, slot, lds_saved[wv],
+                    lds_bnd[wv], &sp);
+            else
+                run_unit<K, kCellU16, false, false, false, false, true>(
+                    P, qs, ts, qm, tm, pos0, pos0 + np, 0, 1, kWave, slot, lds_saved[wv],
+                    lds_bnd[wv], &sp);
+        }
+        __syncthreads();
+        if (nw > 1 && wv == 0 && lane < 2) {
+            unsigned long long key = 0ull;
+            for (int w = 0; w < nw; ++w) key = max(key, s_keys[w * 2 + lane]);
+            PairRef pr = load_pair<false>(P, pos0 + lane, pos0 + np, true);
+            if (s_fail) pr.invalid = true;
+            write_result<false>(P, pr, key);
+            signal_done(P, pr.id);
+        }
+        __syncthreads();
     }
 }
 
@@ -1374,6 +1648,12 @@ hipError_t launch_persistent_t(const KParams &p, int cols, int grid, hipStream_t
                            0, stream, p);
     else
         return hipErrorInvalidValue;
+    return hipGetLastError();
+}
+
+hipError_t launch_split(const KParams &p, int cols, int waves, int grid, hipStream_t stream) {
+    if (cols != 16 || waves != 4) return hipErrorInvalidValue;
+    hipLaunchKernelGGL((split_kernel<16, 4>), dim3(grid), dim3(kWave * 4), 0, stream, p);
     return hipGetLastError();
 }
 

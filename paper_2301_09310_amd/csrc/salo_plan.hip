@@ -195,7 +195,7 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_top(KParams P, BinTabl
     if (t == 0) {
         // bins appear in descending index order in the sorted list; units
         // are numbered within each bin's column class
-        int32_t first = 0, unit0[kColClasses] = {0, 0, 0};
+        int32_t first = 0, unit0[kColClasses] = {0, 0, 0, 0};
         for (int b = kMaxBins - 1; b >= 0; --b) {
             BinDesc d;
             const bool on = b < bt.n_bins;
@@ -206,7 +206,8 @@ __global__ __launch_bounds__(kScanThreads) void plan_scan_top(KParams P, BinTabl
             d.count = on ? pb.binstat[3 * b + 0] : 0;
             d.first = first;
             d.units = (d.count + d.pairs - 1) / d.pairs;
-            const int kc = col_class(d.cols);
+            d.split = on ? bt.split[b] : 0;
+            const int kc = bin_class(d.cols, d.split);
             d.unit0 = unit0[kc];
             d.n_min = on ? pb.binstat[3 * b + 1] : 0;
             d.n_max = on ? pb.binstat[3 * b + 2] : 0;

@@ -35,7 +35,7 @@ class Options(ctypes.Structure):
     _fields_ = [("mode", ctypes.c_int32), ("lanes", ctypes.c_int32),
                 ("cols", ctypes.c_int32), ("force_int32", ctypes.c_int32),
                 ("waves_per_cu", ctypes.c_int32), ("timing", ctypes.c_int32),
-                ("no_f16", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+                ("no_f16", ctypes.c_int32), ("split_waves", ctypes.c_int32)]
 
 
 class Bin(ctypes.Structure):
@@ -122,8 +122,9 @@ def _stream_handle(stream):
 
 
 def make_options(mode="auto", lanes=0, cols=0, force_int32=False, waves_per_cu=0,
-                 timing=False, no_f16=False):
+                 timing=False, no_f16=False, split_waves=0):
     o = Options()
+    o.split_waves = int(split_waves)
     o.timing = 1 if timing else 0
     o.no_f16 = 1 if no_f16 else 0
     o.mode = _MODES[mode] if isinstance(mode, str) else int(mode)
@@ -153,7 +154,7 @@ def align_batch(q_seqs, q_offsets, t_seqs, t_offsets, scoring=(1, -4, 6, 1),
     q_nmask / t_nmask: optional int32 CUDA tensors, one bit per base marking
     N (salo_align_batch_n).  With no options and no masks the call goes
     to salo_align_batch itself, else to salo_align_batch_ex.  Keyword
-    options: mode ('auto' | 'plain' | 'persistent'), lanes, cols,
+    options: mode ('auto' | 'plain' | 'persistent'), lanes, cols, split_waves,
     force_int32, no_f16, waves_per_cu, timing.
     """
     import torch

@@ -110,7 +110,8 @@ class GpuExecutor:
 
     def __init__(self, n_slots: int = 3, max_pairs: int = 1 << 17,
                  max_bytes: int = 96 << 20, scoring=(1, -4, 6, 1), device="cuda",
-                 per_request: bool = True, **options):
+                 per_request: bool = True, split_waves: int = 0,
+                 split_max_long: int = 1024, **options):
         import torch
         from paper_2301_09310_amd import salo
         salo.load()
@@ -119,6 +120,13 @@ class GpuExecutor:
         self.scoring = scoring
         self.options = options
         self.per_request = per_request
+        # long pairs (queries above 1024 bases) run on split_waves waves each
+        # when a launch holds at most split_max_long of them: then the GPU
+        # has room for every split unit at once and the split only shortens
+        # the launch; with more, splitting would cost throughput
+        self.split_waves = int(split_waves)
+        self.split_max_long = int(split_max_long)
+        self.launch_split = []
         self.max_pairs = int(max_pairs)
         self.max_bytes = int(max_bytes)
         self.slots = []
@@ -169,6 +177,12 @@ class GpuExecutor:
             sl["done"].array[:len(reqs)] = 0
         # the stream waits for the previous launch on this slot before the
         # staging copies overwrite its device buffers (stream order)
+        opts = dict(self.options)
+        if self.split_waves > 1:
+            n_long = sum(int((r.batch.q_lens() > 1024).sum()) for r in reqs)
+            if n_long <= self.split_max_long:
+                opts["split_waves"] = self.split_waves
+            self.launch_split.append(opts.get("split_waves", 0))
         with torch.cuda.stream(s):
             d["q"][:m.q_bytes].copy_(h["q"][:m.q_bytes], non_blocking=True)
             d["t"][:m.t_bytes].copy_(h["t"][:m.t_bytes], non_blocking=True)
@@ -180,13 +194,11 @@ class GpuExecutor:
                 outs = (base, base + 4 * self.max_pairs, base + 8 * self.max_pairs)
                 self.salo.align_batch_tagged(d["q"][:m.q_bytes], d["qo"][:n + 1],
                                              d["t"][:m.t_bytes], d["to"][:n + 1], self.scoring,
-                                             outs, d["tag"], sl["done"].ptr, stream=s,
-                                             **self.options)
+                                             outs, d["tag"], sl["done"].ptr, stream=s, **opts)
             else:
                 out = (d["out"][0, :n], d["out"][1, :n], d["out"][2, :n])
                 self.salo.align_batch(d["q"][:m.q_bytes], d["qo"][:n + 1], d["t"][:m.t_bytes],
-                                      d["to"][:n + 1], self.scoring, out=out, stream=s,
-                                      **self.options)
+                                      d["to"][:n + 1], self.scoring, out=out, stream=s, **opts)
                 for c in range(3):
                     h["out"][c, :n].copy_(d["out"][c, :n], non_blocking=True)
             sl["event"].record(s)

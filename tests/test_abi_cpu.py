@@ -84,7 +84,7 @@ def test_misaligned_stream(lib):
 
 def test_bad_options(lib):
     o = salo.make_options()
-    o.reserved = 3
+    o.split_waves = 3
     assert _call(5, opts=o) == -1
     o = salo.make_options()
     o.no_f16 = 2

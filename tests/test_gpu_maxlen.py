@@ -101,3 +101,18 @@ def test_trace(dev, batch):
     for p in (1, 3):
         assert ln[p] == wln[p]
         assert np.array_equal(cig[off[p]:off[p] + ln[p]], wcig[woff[p]:woff[p] + wln[p]])
+
+
+def test_forward_split_waves(dev, batch):
+    """The maximum lengths with split_waves = 4: a 65,535-row unit in four
+    strips of 16,384 rows (each strip's column fills half its slot)."""
+    import torch
+    from paper_2301_09310_amd import salo
+    b = batch
+    _say("maxlen forward, split waves")
+    q, qo, t, to = salo.to_device(b)
+    got = salo.align_batch(q, qo, t, to, split_waves=4)
+    torch.cuda.synchronize()
+    want = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets)
+    for g, w in zip(got, want):
+        assert np.array_equal(g.cpu().numpy().astype(np.int64), w)

@@ -463,3 +463,40 @@ def test_growth_after_capture_keeps_the_graph_valid(dev):
         torch.cuda.synchronize()
         got = tuple(x.cpu().numpy().astype(np.int64) for x in out)
         assert_same(small, got, want_s, "replay %d after growth" % rep)
+
+
+@pytest.mark.parametrize("case", ["long_uneven", "mixed", "random", "edges"])
+def test_split_waves_match_the_oracle(dev, case):
+    """split_waves = 4: the 64-lane bins' units run on four waves each, one
+    strip of target rows per wave; every answer equals the oracle's
+    (strip boundaries inside alignments, pairs of one unit with different
+    lengths, units too short to split, 32-bit cells)."""
+    if case == "long_uneven":
+        b = I.long_uneven(0, 600)
+    elif case == "mixed":
+        b = I.mixed(2, 4000)
+    elif case == "random":
+        b = I.random_pairs(57, 800, 3000, min_len=200, related=0.7)
+    else:
+        # identical strings (the best cell is the last row), one long pair
+        # beside a short one, rows just above and below the split threshold
+        rng = np.random.default_rng(58)
+        qs, ts = [], []
+        for n in (1024, 1023, 1025, 2048, 2047, 4096, 5000, 257, 1100, 3333):
+            t = rng.integers(0, 4, n).astype(np.uint8)
+            qs.append(t.copy())
+            ts.append(t)
+        for m, n in ((3000, 5000), (2500, 400), (1200, 9000), (5000, 1030)):
+            t = rng.integers(0, 4, n).astype(np.uint8)
+            q = rng.integers(0, 4, m).astype(np.uint8)
+            k = min(m, n) // 2
+            q[:k] = t[n - k:]
+            qs.append(q)
+            ts.append(t)
+        b = I.from_codes(qs, ts)
+    want = oracle_align(b)
+    _say("split waves", case, b.n_pairs)
+    assert_same(b, gpu_align(b, split_waves=4), want, "split %s" % case)
+    if case == "random":
+        assert_same(b, gpu_align(b, split_waves=4, force_int32=True), want, "split int32")
+        assert_same(b, gpu_align(b, split_waves=4, no_f16=True), want, "split u16")

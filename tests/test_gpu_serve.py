@@ -48,8 +48,10 @@ def test_alone_equals_mix(dev):
 
 def test_served_requests_of_full_size(dev):
     """Requests of the served stream's own sizes (1..4,096 pairs of the
-    mixed workload, including both extremes), arriving while others run:
-    each served result equals the oracle and the same request alone."""
+    mixed workload, including both extremes), arriving while others run, in
+    the bench's serving configuration (per-request completion, long pairs
+    on four waves): each served result equals the oracle and the same
+    request aligned alone."""
     import torch
     from paper_2301_09310_amd import salo
     pool = I.mixed(0, 40_000)
@@ -57,7 +59,7 @@ def test_served_requests_of_full_size(dev):
     sizes[0], sizes[1] = 4096, 1
     arrivals = S.poisson_arrivals(len(sizes), 400.0, 21)
     reqs = S.split_requests(pool, sizes, arrivals)
-    ex = S.GpuExecutor(n_slots=3, max_pairs=1 << 15, max_bytes=32 << 20)
+    ex = S.GpuExecutor(n_slots=3, max_pairs=1 << 15, max_bytes=32 << 20, split_waves=4)
     budget = 3 * max(S.footprint_bytes(r.batch) for r in reqs)
     print("[case] serve %d requests of %s pairs, budget %d" % (
         len(reqs), sizes.tolist(), budget), flush=True)

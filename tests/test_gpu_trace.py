@@ -180,7 +180,7 @@ def test_trace_on_side_stream(dev):
     st = salo.align_starts(q, qo, t, to, ans)
     side = torch.cuda.Stream()
     off, cig, ln = salo.align_trace(q, qo, t, to, ans, st, stream=side,
-                                    workspace_bytes=1 << 28)
+                                    workspace_bytes=1 << 30)
     # churn the allocator on the current stream while the side stream runs
     junk = [torch.empty(1 << 26, dtype=torch.uint8, device=dev).fill_(0xAB) for _ in range(4)]
     side.synchronize()
@@ -191,6 +191,7 @@ def test_trace_on_side_stream(dev):
     w_st = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *w_ans)
     woff, wcig, wln = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, w_ans[0],
                                     w_st[0], w_ans[1], w_st[1], w_ans[2])
+    assert salo.error_count(side) == 0
     assert np.array_equal(cpu(off), woff)
     assert np.array_equal(cpu(ln), wln)
     g = cig.cpu().numpy().view(np.uint32)
