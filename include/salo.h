@@ -337,16 +337,21 @@ salo_status_t salo_pack_bases(const uint8_t *chars, int64_t n_chars, const int64
 /*
  * salo_align_batch_ex with per-request completion, for serving several
  * requests merged into one call: pair p belongs to request pair_tag[p]
- * (DEVICE int32 [n_pairs]; a negative tag means no request), and as soon
- * as pair p's three outputs are written the library adds 1 to
- * tag_done[pair_tag[p]] with a system-scope release, so a host thread that
- * reads tag_done[r] == (pairs of request r) can read that request's outputs
- * while the rest of the call still runs.  tag_done must be host memory the
- * device can update coherently (salo_host_alloc) and must hold every tag
- * used; the caller zeroes the counters before the call.  When the output
- * arrays are also such host memory, they need no copy back.  Arguments,
- * options, layout and errors otherwise as salo_align_batch_ex (NULL
- * pair_tag or tag_done with n_pairs > 0: SALO_ERR_INVALID).
+ * (DEVICE int32 [n_pairs]; a negative tag means no request), and once
+ * pair p's three outputs are written the library adds 1 to
+ * tag_done[pair_tag[p]], so a host thread that reads tag_done[r] == (pairs
+ * of request r) can read that request's outputs while the rest of the call
+ * still runs.  tag_done and the three output arrays must be host memory
+ * from salo_host_alloc: the device writes the outputs through to it and
+ * issues each count after those stores have completed.  tag_done must hold
+ * every tag used, and the caller zeroes the counters before the call.
+ * Counters that share a 128-byte line contend (the device's increments of
+ * one line are serialised): give each request a line of its own, e.g. tags
+ * 32 apart.  Outputs in device memory are written as usual, but the counts
+ * then do not order them for the host: read them after the stream has
+ * passed the call.  Arguments, options, layout and errors otherwise as
+ * salo_align_batch_ex (NULL pair_tag or tag_done with n_pairs > 0:
+ * SALO_ERR_INVALID).
  */
 salo_status_t salo_align_batch_tagged(const uint8_t *q_seqs, const int64_t *q_offsets,
                                       const uint8_t *t_seqs, const int64_t *t_offsets,

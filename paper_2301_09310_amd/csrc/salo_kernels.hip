@@ -346,26 +346,33 @@ __device__ __forceinline__ void write_result(const KParams &P, const PairRef &pr
         P.out_tend[pr.id] = s > 0 ? (pr.n - 1) - ir : -1;
         return;
     }
-    if (pr.invalid) {
-        P.out_score[pr.id] = -1; P.out_qend[pr.id] = -1; P.out_tend[pr.id] = -1;
-        atomicAdd(P.errors, 1ull);
-        return;
-    }
-    const int32_t s = (int32_t)(key >> 32);
-    P.out_score[pr.id] = s;
-    P.out_qend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)(key & 0xFFFF)) : -1;
-    P.out_tend[pr.id] = s > 0 ? (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF)) : -1;
+    // System-scope stores write through the L2, so that signal_done can
+    // announce them to the host without writing back the whole L2 (12 bytes
+    // per pair; device-memory outputs take the same path).
+    const int32_t s = pr.invalid ? -1 : (int32_t)(key >> 32);
+    const int32_t qe = pr.invalid ? -1 : s > 0 ? (int32_t)(0xFFFFu - (uint32_t)(key & 0xFFFF)) : -1;
+    const int32_t te =
+        pr.invalid ? -1 : s > 0 ? (int32_t)(0xFFFFu - (uint32_t)((key >> 16) & 0xFFFF)) : -1;
+    __hip_atomic_store(P.out_score + pr.id, s, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(P.out_qend + pr.id, qe, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    __hip_atomic_store(P.out_tend + pr.id, te, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+    if (pr.invalid) atomicAdd(P.errors, 1ull);
 }
 
 // Per-request completion: count pair `id` as finished for its tag.  The
-// release at system scope makes the pair's outputs (this lane's stores
-// above) visible to the host before the count that announces them.
+// outputs and the counters live in coherent host memory (salo_host_alloc).
+// write_result stored the outputs at system scope (through the L2); once
+// those stores have completed they are visible to the host, and the count
+// that announces them is issued only then.  (A release fence at system
+// scope would do the same by writing back the whole L2 at every call.)
 __device__ __forceinline__ void signal_done(const KParams &P, int32_t id) {
     if (P.pair_tag == nullptr || id < 0) return;
     const int32_t tg = P.pair_tag[id];
-    if (tg >= 0)
-        __hip_atomic_fetch_add(P.tag_done + tg, 1u, __ATOMIC_RELEASE,
+    if (tg >= 0) {
+        asm volatile("s_waitcnt vmcnt(0)" ::: "memory");
+        __hip_atomic_fetch_add(P.tag_done + tg, 1u, __ATOMIC_RELAXED,
                                __HIP_MEMORY_SCOPE_SYSTEM);
+    }
 }
 
 // Trace pass: choice codes, one nibble per cell, as the fill stores them.
