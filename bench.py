@@ -260,9 +260,9 @@ def main(argv=None) -> int:
                     help="most pairs merged into one launch")
     ap.add_argument("--serve-rates", default="0.5,0.8",
                     help="offered loads as fractions of the saturated rate")
-    ap.add_argument("--serve-split", type=int, default=4,
-                    help="split_waves of the served launches (4: long pairs on four waves "
-                         "each; 0: off)")
+    ap.add_argument("--serve-split", type=int, default=0,
+                    help="split_waves of the served launches (0: off; 4: long pairs on four "
+                         "waves each in launches with at most 1024 of them)")
     ap.add_argument("--serve-per-launch", action="store_true",
                     help="complete requests when their whole merged launch ends (no "
                          "per-request counters)")
@@ -956,7 +956,8 @@ def serve_block(args, pool):
     return {"requests": args.serve_requests, "warmup_requests": args.serve_warmup,
             "completion": "per launch" if args.serve_per_launch else "per request",
             "split_waves": args.serve_split,
-            "split_rule": "launches with at most 1024 queries above 1024 bases",
+            "split_rule": ("launches with at most 1024 queries above 1024 bases"
+                           if args.serve_split > 1 else None),
             "pairs_per_request": "U{1..4096}", "arrivals": "Poisson (seed 1)",
             "budget_gb": args.serve_budget_gb, "slots": args.serve_slots,
             "launch_pairs": args.serve_launch_pairs,

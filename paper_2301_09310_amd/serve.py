@@ -101,6 +101,12 @@ class Merged:
         return starts
 
 
+# Each request's completion counter gets its own 128-byte line (tags step
+# by 32 counters): the device's system-scope increments of one line are
+# serialised, and with adjacent counters a merged launch ran 20% longer.
+TAG_STRIDE = 32
+
+
 class GpuExecutor:
     """Runs launches on `n_slots` HIP streams, each with buffers sized for
     `max_pairs` pairs and `max_bytes` packed bytes per sequence stream.
@@ -147,7 +153,9 @@ class GpuExecutor:
                 # results and per-request counters in coherent host memory:
                 # the kernel writes them, the loop reads them while it runs
                 slot["res"] = salo.HostBuffer(3 * self.max_pairs, np.int32)
-                slot["done"] = salo.HostBuffer(self.max_pairs, np.uint32)
+                # a request takes at least one pair and one pad pair
+                slot["done"] = salo.HostBuffer((self.max_pairs // 2 + 1) * TAG_STRIDE,
+                                               np.uint32)
             salo.reserve(self.max_pairs, stream=s)
             self.slots.append(slot)
         self.free = list(range(n_slots))
@@ -172,9 +180,9 @@ class GpuExecutor:
         if self.per_request:
             tag = h["tag"].numpy()
             for i, (r, p) in enumerate(zip(reqs, starts)):
-                tag[p:p + r.batch.n_pairs] = i
+                tag[p:p + r.batch.n_pairs] = i * TAG_STRIDE
                 tag[p + r.batch.n_pairs] = -1          # the pad pair after the request
-            sl["done"].array[:len(reqs)] = 0
+            sl["done"].array[:len(reqs) * TAG_STRIDE] = 0
         # the stream waits for the previous launch on this slot before the
         # staging copies overwrite its device buffers (stream order)
         opts = dict(self.options)
@@ -223,7 +231,7 @@ class GpuExecutor:
         done = sl["done"].array
         out = []
         for i, (r, p) in enumerate(parts):
-            if i not in reported and int(done[i]) == r.batch.n_pairs:
+            if i not in reported and int(done[i * TAG_STRIDE]) == r.batch.n_pairs:
                 reported.add(i)
                 out.append((i, self._result(sl, r, p)))
         return out
