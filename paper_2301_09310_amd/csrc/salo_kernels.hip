@@ -201,6 +201,9 @@ struct Slot {
 //    a load and a store per row, and each row is read from LDS.
 constexpr uint32_t kBndLdsBytes = 4096;
 constexpr uint32_t kBndBlockBytes = 1024;
+// a wave clears the region with four 16-byte stores per lane
+static_assert(kBndLdsBytes == 4 * kBndBlockBytes && kBndBlockBytes == 16 * kWave,
+              "boundary column layout");
 
 __device__ __forceinline__ uint2 lds_load8(const uint32_t *lds, uint32_t byte_off) {
     return *reinterpret_cast<const uint2 *>(reinterpret_cast<const char *>(lds) + byte_off);
@@ -232,6 +235,12 @@ __device__ __forceinline__ uint32_t shift_in(uint32_t v, uint32_t bnd, bool firs
 __device__ __forceinline__ int wave_max(int v) {
 #pragma unroll
     for (int o = 32; o >= 1; o >>= 1) v = max(v, __shfl_xor(v, o, kWave));
+    return __builtin_amdgcn_readfirstlane(v);
+}
+
+__device__ __forceinline__ int wave_min_i32(int v) {
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) v = min(v, __shfl_xor(v, o, kWave));
     return __builtin_amdgcn_readfirstlane(v);
 }
 
@@ -666,6 +675,12 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
     for (int h = 0; h < NPG; ++h)
         lim[h] = SPL ? max(0, min(pr[h].n, sp->r_hi) - v_lo) : pr[h].n;
+    // the fewest rows of any pair of this pass's groups (the lanes of other
+    // groups compute values nothing reads)
+    int lim_min = 0x7FFFFFFF;
+#pragma unroll
+    for (int h = 0; h < NPG; ++h) lim_min = mine ? min(lim_min, lim[h]) : lim_min;
+    lim_min = wave_min_i32(lim_min);
     // unbanded: the column in LDS, resident when the whole column fits, else
     // through the rings (Gs is then a power of two, so a 1 KiB block holds
     // SB = 128 / Gs whole rows)
@@ -793,8 +808,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
         for (int h = 0; h < NPG; ++h) crow[h] = -1;
         // 16-bit cells: which of the lane's two row buffers holds each pair's
-        // saved row; a row where both pairs improve is saved once for both
-        int sbA = 0, sbB = 1;
+        // saved row, one bit per lane of the wave (set: buffer 1); a row where
+        // both pairs improve is saved once for both
+        uint64_t sbA = 0ull, sbB = ~0ull;
 
         const bool have_bnd = c > 0;   // implies R >= 1 (C == 0 when R == 0)
         const bool write_bnd = c + 1 < C;
@@ -845,17 +861,31 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 fifo[r] = make_uint2(0u, 0u);
                 if (have_bnd) fifo[r] = bslot.load(slot_off(r0 + r));
             }
-        } else if (have_bnd) {
-            if (!bnd_res) {
-                // blocks 0 and 1 into the read ring, then block 2 in flight
-                const uint4 b0 = bslot.load16(lane16);
-                const uint4 b1 = bslot.load16(kBndBlockBytes + lane16);
-                lds_store16(lds_bnd, lane16, b0);
-                lds_store16(lds_bnd, kBndBlockBytes + lane16, b1);
+        } else {
+            if (have_bnd) {
+                if (!bnd_res) {
+                    // blocks 0 and 1 into the read ring, then block 2 in flight
+                    const uint4 b0 = bslot.load16(lane16);
+                    const uint4 b1 = bslot.load16(kBndBlockBytes + lane16);
+                    lds_store16(lds_bnd, lane16, b0);
+                    lds_store16(lds_bnd, kBndBlockBytes + lane16, b1);
+                    wave_sync();
+                    inflight = bslot.load16(2u * kBndBlockBytes + lane16);
+                }
+            } else {
+                // the first chunk has no boundary: it reads zeros from the
+                // column (resident) or from the read ring, which no block
+                // event refills during this chunk
+                const uint4 z = make_uint4(0u, 0u, 0u, 0u);
+                lds_store16(lds_bnd, lane16, z);
+                lds_store16(lds_bnd, kBndBlockBytes + lane16, z);
+                if (bnd_res) {
+                    lds_store16(lds_bnd, 2u * kBndBlockBytes + lane16, z);
+                    lds_store16(lds_bnd, 3u * kBndBlockBytes + lane16, z);
+                }
                 wave_sync();
-                inflight = bslot.load16(2u * kBndBlockBytes + lane16);
             }
-            bnd_cur = lds_load8(lds_bnd, ld_lane);      // row 0 (R >= 1 here)
+            bnd_cur = lds_load8(lds_bnd, ld_lane);      // row 0
         }
         if constexpr (BAND) {
             // lane 0's first diagonal: H(r0 - 1, c0 - 1), inside the band
@@ -904,7 +934,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         // `bulk` (compile time, unbanded): every step of the range has
         // s >= W - 1 and s + 1 < Rc, so the step-range checks of the
         // boundary reader and writer are left out
-        auto run_steps = [&](int sa, int sb, auto masked, auto frozen, auto bulk) {
+        auto run_steps = [&](int sa, int sb, auto masked, auto frozen, auto bulk,
+                             auto full) {
         for (int s0 = sa; s0 < sb; s0 += 4) {
             if ((s0 & 15) == 0) {
                 // the next 16 target bases of each pair, already in flight;
@@ -928,6 +959,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             constexpr bool MASK = BAND && decltype(masked)::value;
             constexpr bool FROZEN = SPL && decltype(frozen)::value;
             constexpr bool BULK = !BAND && decltype(bulk)::value;
+            // every row of every lane lies below each of its pairs' ends
+            // (and at or above row 0): no per-pair range test
+            constexpr bool FULL = BULK && !NM && decltype(full)::value;
 #pragma unroll
             for (int j = 0; j < 4; ++j) {
                 const int s = s0 + j;
@@ -939,16 +973,15 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     if (have_bnd) fifo[j & 3] = bslot.load(slot_off(r0 + s + 4));
                 } else {
                     bnd = bnd_cur;
-                    if (have_bnd) {
-                        // row rn = s + 1 for the next step (rows past the
-                        // column read as 0); in ring mode its block is in
-                        // the read ring (see the block events below)
-                        const int rn = s + 1;
-                        bnd_cur = (BULK || rn < Rc)
-                                      ? lds_load8(lds_bnd, (((uint32_t)rn * row_bytes) & bnd_mask) +
-                                                               ld_lane)
-                                      : make_uint2(0u, 0u);
-                    }
+                    // row rn = s + 1 for the next step (rows past the column
+                    // read as 0); in ring mode its block is in the read ring
+                    // (see the block events below); the first chunk reads
+                    // the zeros its start cleared
+                    const int rn = s + 1;
+                    bnd_cur = (BULK || rn < Rc)
+                                  ? lds_load8(lds_bnd,
+                                              (((uint32_t)rn * row_bytes) & bnd_mask) + ld_lane)
+                                  : make_uint2(0u, 0u);
                 }
                 // banded: bit k set when column col0 + k of row i is in the band
                 uint32_t bmask = 0xFFFFFFFFu;
@@ -961,6 +994,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                 auto inband = [&](int k) -> uint32_t {
                     return MASK ? (uint32_t)((int32_t)(bmask << (31 - k)) >> 31) : 0xFFFFFFFFu;
                 };
+                // packed cells: this row's maxima of a live lane (0 otherwise),
+                // for the first-maximum tracking after the lane's step
+                uint32_t rowmax_live = 0;
                 if (!FROZEN || l <= s) {
                 const uint32_t hin = shift_in(hout, bnd.x, first_lane);
                 const uint32_t ein = shift_in(eout, bnd.y, first_lane);
@@ -978,10 +1014,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     // operand); F may go negative, down to -alpha
                     const uint32_t bA = (tw[0] >> (jsh + 2 * j)) & 3u;
                     const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
-                    const uint32_t TA =
-                        (uint32_t)(i - v_lo) < (uint32_t)lim[0] ? (MM4 ^ (XM << (bA << 3))) : 0u;
-                    const uint32_t TB =
-                        (uint32_t)(i - v_lo) < (uint32_t)lim[1] ? (MM4 ^ (XM << (bB << 3))) : 0u;
+                    const uint32_t TA = (FULL || (uint32_t)(i - v_lo) < (uint32_t)lim[0])
+                                            ? (MM4 ^ (XM << (bA << 3))) : 0u;
+                    const uint32_t TB = (FULL || (uint32_t)(i - v_lo) < (uint32_t)lim[1])
+                                            ? (MM4 ^ (XM << (bB << 3))) : 0u;
                     // the diagonal term of column k+1 is formed in column
                     // k's step, from H[k] before it takes row i: it is
                     // independent of the E chain (hh, ha, e), so it fills
@@ -1008,8 +1044,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     const uint32_t bB = (tw[1] >> (jsh + 2 * j)) & 3u;
                     // rows past the pair's end (and N rows) get the zero
                     // table: a mismatch in every column
-                    bool okA = (uint32_t)(i - v_lo) < (uint32_t)lim[0];
-                    bool okB = (uint32_t)(i - v_lo) < (uint32_t)lim[1];
+                    bool okA = FULL || (uint32_t)(i - v_lo) < (uint32_t)lim[0];
+                    bool okB = FULL || (uint32_t)(i - v_lo) < (uint32_t)lim[1];
                     if constexpr (NM) {
                         okA = okA && !((tn[0] >> ((s0 & 15) + j)) & 1u);
                         okB = okB && !((tn[1] >> ((s0 & 15) + j)) & 1u);
@@ -1078,7 +1114,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         }
                     }
                 } else {
-                    bool okt = (uint32_t)(i - v_lo) < (uint32_t)lim[0];
+                    bool okt = FULL || (uint32_t)(i - v_lo) < (uint32_t)lim[0];
                     if constexpr (NM) okt = okt && !((tn[0] >> ((s0 & 15) + j)) & 1u);
                     // 4 never equals a query code (0..3, or 5 past the end / N)
                     const uint32_t tb = okt ? ((tw[0] >> (jsh + 2 * j)) & 3u) : 4u;
@@ -1150,33 +1186,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         }
                     }
                 }
-                // row-level tracking of the first maximum
+                // row-level tracking of the first maximum (packed cells: after
+                // the live-lane block, so that the wave-wide masks below are
+                // formed in uniform control flow)
                 if constexpr (PK) {
-                    const uint32_t nb = pmax(cbest, rowmax);
-                    const uint32_t chg = nb ^ cbest;
-                    cbest = nb;
-                    if (chg != 0u) {
-                        // one save per row: both pairs improving share a
-                        // buffer; one pair alone takes a buffer the other
-                        // pair's saved row is not in
-                        const bool cA = (chg & 0xFFFFu) != 0u, cB = (chg >> 16) != 0u;
-                        const int x = (cA && cB) ? 0
-                                      : cA ? (sbA == sbB ? 1 - sbB : sbA)
-                                           : (sbA == sbB ? 1 - sbA : sbB);
-                        if (cA) {
-                            crow[0] = i;
-                            sbA = x;
-                        }
-                        if (cB) {
-                            crow[1] = i;
-                            sbB = x;
-                        }
-                        uint32_t *dst = my_saved + x * K;
-#pragma unroll
-                        for (int k = 0; k < K; k += 4)
-                            *reinterpret_cast<uint4 *>(dst + k) =
-                                make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
-                    }
+                    rowmax_live = rowmax;
                 } else {
                     if ((int)rowmax > (int)cbest) {
                         cbest = rowmax;
@@ -1188,6 +1202,39 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     }
                 }
                 }  // live lane
+                if constexpr (PK) {
+                    const uint32_t rowmax = rowmax_live;
+                    // pair A in the low halves, pair B in the high halves;
+                    // non-negative binary16 values order as their bits do
+                    const bool cA = (rowmax & 0xFFFFu) > (cbest & 0xFFFFu);
+                    const bool cB = (rowmax >> 16) > (cbest >> 16);
+                    cbest = pmax(cbest, rowmax);
+                    const uint64_t mA = __builtin_amdgcn_ballot_w64(cA);
+                    const uint64_t mB = __builtin_amdgcn_ballot_w64(cB);
+                    if ((mA | mB) != 0ull) {
+                        // one save per row, the buffer chosen per lane with
+                        // wave-wide masks: one pair improving alone takes the
+                        // buffer the other pair's saved row is not in (the
+                        // other buffer when both sit in one); both improving
+                        // take pair A's
+                        const uint64_t alone_eq = (mA ^ mB) & ~(sbA ^ sbB);
+                        const uint64_t onlyB = mB & ~mA;
+                        const uint64_t x = (alone_eq & ~sbA) |
+                                           (~alone_eq & ((onlyB & sbB) | (~onlyB & sbA)));
+                        sbA = (sbA & ~mA) | (x & mA);
+                        sbB = (sbB & ~mB) | (x & mB);
+                        if (cA) crow[0] = i;
+                        if (cB) crow[1] = i;
+                        if (cA || cB) {
+                            uint32_t *dst =
+                                my_saved + (__builtin_amdgcn_inverse_ballot_w64(x) ? K : 0);
+#pragma unroll
+                            for (int k = 0; k < K; k += 4)
+                                *reinterpret_cast<uint4 *>(dst + k) =
+                                    make_uint4(H[k], H[k + 1], H[k + 2], H[k + 3]);
+                        }
+                    }
+                }
                 // the group's last lane holds row r0 + s - (W-1): one of the
                 // chunk's rows once s >= W-1 (and never past them, as
                 // s < nrows + W - 1)
@@ -1244,26 +1291,31 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             // inside that range skip the mask
             const int a = min(max(0, (s_lo + 3) & ~3), (S + 3) & ~3);
             const int b = max(a, min(((s_hi + 1) & ~3), (S + 3) & ~3));
-            run_steps(0, a, std::true_type{}, std::false_type{}, std::false_type{});
-            run_steps(a, b, std::false_type{}, std::false_type{}, std::false_type{});
-            run_steps(b, S, std::true_type{}, std::false_type{}, std::false_type{});
+            run_steps(0, a, std::true_type{}, std::false_type{}, std::false_type{}, std::false_type{});
+            run_steps(a, b, std::false_type{}, std::false_type{}, std::false_type{}, std::false_type{});
+            run_steps(b, S, std::true_type{}, std::false_type{}, std::false_type{}, std::false_type{});
         } else {
             // head (the wavefront's ramp: lanes before their first row; a
             // strip below the first keeps them frozen), bulk, tail (rows
             // past the column); the N-mask and trace kernels, which hold
             // more registers, keep one loop with the checks in every step
+            // (bulk steps below `f` run every lane's row inside each of its
+            // pairs, so they skip the per-pair range test)
             const int a = min((W - 1 + 3) & ~3, (S + 3) & ~3);
             const int b = max(a, (Rc - 1) & ~3);
+            const int f = max(a, min(b, lim_min & ~3));
             if (SPL && sp->ws > 0) {
-                run_steps(0, a, std::false_type{}, std::true_type{}, std::false_type{});
-                run_steps(a, b, std::false_type{}, std::false_type{}, std::true_type{});
-                run_steps(b, S, std::false_type{}, std::false_type{}, std::false_type{});
+                run_steps(0, a, std::false_type{}, std::true_type{}, std::false_type{}, std::false_type{});
+                run_steps(a, f, std::false_type{}, std::false_type{}, std::true_type{}, std::true_type{});
+                run_steps(f, b, std::false_type{}, std::false_type{}, std::true_type{}, std::false_type{});
+                run_steps(b, S, std::false_type{}, std::false_type{}, std::false_type{}, std::false_type{});
             } else if constexpr (!NM && !TR) {
-                run_steps(0, a, std::false_type{}, std::false_type{}, std::false_type{});
-                run_steps(a, b, std::false_type{}, std::false_type{}, std::true_type{});
-                run_steps(b, S, std::false_type{}, std::false_type{}, std::false_type{});
+                run_steps(0, a, std::false_type{}, std::false_type{}, std::false_type{}, std::false_type{});
+                run_steps(a, f, std::false_type{}, std::false_type{}, std::true_type{}, std::true_type{});
+                run_steps(f, b, std::false_type{}, std::false_type{}, std::true_type{}, std::false_type{});
+                run_steps(b, S, std::false_type{}, std::false_type{}, std::false_type{}, std::false_type{});
             } else {
-                run_steps(0, S, std::false_type{}, std::false_type{}, std::false_type{});
+                run_steps(0, S, std::false_type{}, std::false_type{}, std::false_type{}, std::false_type{});
             }
         }
         if constexpr (!BAND) {
@@ -1295,7 +1347,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
                 for (int k = K - 1; k >= 0; --k) {
                     const uint32_t hv =
-                        PK ? ((my_saved[(h ? sbB : sbA) * K + k] >> (16 * h)) & 0xFFFFu)
+                        PK ? ((my_saved[(__builtin_amdgcn_inverse_ballot_w64(h ? sbB : sbA)
+                                             ? K : 0) + k] >> (16 * h)) & 0xFFFFu)
                            : my_saved[k];
                     if (hv == v) kk = k;
                 }
