@@ -252,7 +252,8 @@ def main(argv=None) -> int:
                     help="leave the served-stream block out of the mixed-workload line")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-warmup", type=int, default=100)
-    ap.add_argument("--serve-pool", type=int, default=1_000_000)
+    ap.add_argument("--serve-pool", type=int, default=4_000_000,
+                    help="pairs of the mixed workload the requests are carved from")
     ap.add_argument("--serve-budget-gb", type=float, default=32.0)
     ap.add_argument("--serve-slots", type=int, default=3,
                     help="launches in flight at once (one HIP stream each)")
@@ -544,7 +545,7 @@ def main(argv=None) -> int:
     if args.workload == "mixed" and not args.no_serve and q_nmask is None:
         del q, qo, t, to
         torch.cuda.empty_cache()
-        serve = serve_block(args, batch)
+        serve = serve_in_child(args, batch.n_pairs)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -967,6 +968,35 @@ def serve_block(args, pool):
                           "mean_requests_per_launch": round(sat["mean_requests_per_launch"], 2),
                           "p50_ms": round(sat["p50_ms"], 3), "p99_ms": round(sat["p99_ms"], 3)},
             "rates": runs}
+
+
+def serve_in_child(args, pool_pairs: int):
+    """The served stream of the mixed-workload line, measured by `bench.py
+    --serve` in a process of its own (a server's process: its HIP context and
+    hardware queues hold only the server's streams) on the same pool, the
+    first `pool_pairs` pairs of the mixed workload; its progress goes to this
+    process's stderr."""
+    import subprocess
+    cmd = [sys.executable, os.path.abspath(__file__), "--serve",
+           "--serve-pool", str(pool_pairs),
+           "--serve-requests", str(args.serve_requests),
+           "--serve-warmup", str(args.serve_warmup),
+           "--serve-budget-gb", str(args.serve_budget_gb),
+           "--serve-slots", str(args.serve_slots),
+           "--serve-launch-pairs", str(args.serve_launch_pairs),
+           "--serve-rates", args.serve_rates,
+           "--serve-split", str(args.serve_split)]
+    if args.serve_per_launch:
+        cmd.append("--serve-per-launch")
+    log("serve: in a process of its own: %s" % " ".join(cmd[2:]))
+    r = subprocess.run(cmd, stdout=subprocess.PIPE, text=True, timeout=1800)
+    lines = [ln for ln in r.stdout.splitlines() if ln.startswith("{")]
+    # (exit 1 with a line: the served answers mismatched, which the block says)
+    if r.returncode not in (0, 1) or not lines:
+        raise RuntimeError("served-stream process failed (exit %d)" % r.returncode)
+    blk = json.loads(lines[-1])["serve"]
+    blk["process"] = "own process (bench.py --serve)"
+    return blk
 
 
 def serve_bench(args) -> int:
