@@ -295,9 +295,9 @@ def main(argv=None) -> int:
     compare_plain = not args.no_compare_plain and args.mode != "plain"
 
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
-              "(pairs are independent; see DESIGN.md for how it would shard)",
-              file=sys.stderr)
+        print("bench.py measures one GPU only: there is no multi-GPU path (pairs are "
+              "independent: a batch would shard as contiguous pair ranges of equal cells, "
+              "one process per GPU, with no exchange during compute)", file=sys.stderr)
         return 2
 
     import torch

@@ -233,6 +233,44 @@ def test_persistent_forced_widths(dev, lanes, cols):
                 "persistent lanes=%d cols=%d" % (lanes, cols))
 
 
+def _uneven_rows_batch(seed):
+    """Pairs of one query-length bin whose target lengths differ inside a
+    unit: lengths a few rows apart (one sort level, so they share units:
+    the steps free of the per-pair row test end at the shortest, at any
+    remainder mod 4), lengths far apart (mixed in the plain kernel's
+    consecutive units), and empty and one-row targets.  Half the queries
+    are the target's last bases, so the best cell sits in a pair's last
+    rows, right where the row test starts to matter."""
+    rng = np.random.default_rng(seed)
+    qs, ts = [], []
+    for p in range(1200):
+        m = int(rng.integers(100, 131))
+        n = int(rng.choice([597, 598, 599, 600, 601, 602, 603, 604])) if p % 5 else \
+            int(rng.choice([0, 1, 3, 40, 250, 900]))
+        t = rng.integers(0, 4, n, dtype=np.uint8)
+        if p % 2 == 0 and n >= m:
+            q = t[n - m:].copy()
+            q[rng.integers(0, m, 3)] = rng.integers(0, 4, 3)     # a few substitutions
+        else:
+            q = rng.integers(0, 4, m, dtype=np.uint8)
+        qs.append(q)
+        ts.append(t)
+    return I.from_codes(qs, ts, "uneven_rows")
+
+
+@pytest.mark.parametrize("kw", [{}, {"mode": "plain", "lanes": 4, "cols": 16},
+                                {"mode": "plain", "lanes": 2, "cols": 32},
+                                {"mode": "persistent", "lanes": 8, "cols": 8},
+                                {"mode": "persistent", "lanes": 64, "cols": 16},
+                                {"mode": "persistent", "no_f16": True},
+                                {"mode": "persistent", "force_int32": True}])
+def test_pairs_of_uneven_rows_in_one_unit(dev, kw):
+    b = _uneven_rows_batch(17)
+    want = oracle_align(b)
+    _say("uneven rows in one unit", kw)
+    assert_same(b, gpu_align(b, **kw), want, "uneven rows %s" % kw)
+
+
 def test_modes_agree_on_mixed_lengths(dev):
     """Plain and persistent (binned, sorted) runs give identical outputs."""
     b = I.random_pairs(31, 3000, 1500, related=0.7)
