@@ -83,13 +83,16 @@ def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_source_hash(files=("salo_kernels.hip", "salo_internal.h")) -> str:
-    """sha256 of a kernel's sources (the DP kernel by default); profiler
-    byte counts are only valid for the kernel they were taken on."""
+def kernel_source_hash(files=("csrc/salo_kernels.hip", "csrc/salo_internal.h",
+                              "csrc/salo_host.cpp", "tune_gfx950.json")) -> str:
+    """sha256 of a kernel's sources and of what sets its launch shapes (by
+    default the DP kernels, the host library that picks their tiles, and the
+    compiled-in tile table); profiler byte counts are only valid for the
+    kernel and launch shapes they were taken on."""
     import hashlib
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_2301_09310_amd", "csrc", f), "rb") as fh:
+        with open(os.path.join(ROOT, "paper_2301_09310_amd", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
 
@@ -878,7 +881,7 @@ def pack_bench(args) -> int:
                "sample": "both character streams of the %s batch, forward, %.2fs" % (
                    args.workload, dt)}
     fwd = res["forward"]
-    pack_hash = kernel_source_hash(("salo_pack.hip",))
+    pack_hash = kernel_source_hash(("csrc/salo_pack.hip",))
     rec = {"metric": "packing GB/s (characters in + packed bases out, bit-exact vs oracle)",
            "value": fwd["gbs"], "unit": "GB/s", "n_gpus": 1, "steps": args.steps,
            "warmup": max(args.warmup, 1), "ms_per_step": fwd["ms"], "higher_is_better": True,
