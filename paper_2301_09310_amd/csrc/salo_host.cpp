@@ -314,10 +314,10 @@ BinTable trace_bin_table(int cols, int forced_lanes, int64_t slot_bytes) {
 // the band, so narrow chunks compute fewer cells outside it; but a unit
 // holds 128/W pairs, and a batch with too few units per resident wave ends
 // on a long tail.  Measured on MI355X (200,000 anchored pairs of 500-5,000
-// bases, bands 32..1000): chunks of max(32, w/2) columns rounded down to a
+// bases, bands 32..1000): chunks of max(32, w/4) columns rounded down to a
 // power of two, and at least about two units per wave.
 int band_lanes(int32_t band, int cols, int64_t n_pairs, int64_t grid) {
-    const int64_t target = band / 2 > 32 ? band / 2 : 32;
+    const int64_t target = band / 4 > 32 ? band / 4 : 32;
     int w = 1;
     while (w < 64 && (int64_t)2 * w * cols <= target) w <<= 1;
     while (w < 64 && n_pairs * w < 2 * 128 * grid) w <<= 1;
