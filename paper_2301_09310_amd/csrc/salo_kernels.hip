@@ -61,10 +61,18 @@ __device__ __forceinline__ uint32_t pmax(uint32_t a, uint32_t b) {
 __device__ __forceinline__ uint32_t pmad(uint32_t a, uint32_t b, uint32_t c) {
     return as_u(as_v(a) * as_v(b) + as_v(c));
 }
-// 1 in each half that is non-zero, else 0
-__device__ __forceinline__ uint32_t pnz(uint32_t a) {
-    const u16x2 one = {1, 1};
-    return as_u(__builtin_elementwise_min(as_v(a), one));
+// 1 in each half that is non-zero, else 0, given one = 0x00010001
+__device__ __forceinline__ uint32_t pnz(uint32_t a, uint32_t one) {
+    return as_u(__builtin_elementwise_min(as_v(a), as_v(one)));
+}
+// A constant the optimiser cannot see through (the empty asm emits no
+// instruction).  With literal operands it rewrites min(x, 1) into a compare
+// and a * 16 + c into a shift and an or, and with no packed 16-bit compare
+// it then splits both into per-half compares, selects and repacking; with
+// these operands pnz and pmad stay one packed instruction each.
+__device__ __forceinline__ uint32_t opaque(uint32_t v) {
+    asm volatile("" : "+v"(v));
+    return v;
 }
 // Maximum of three packed cell pairs.  Cell values stay in [0, 0x7BFF]
 // (kPackedLimit), where reading the bits as binary16 gives finite,
@@ -797,11 +805,25 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         uint32_t facc[TR && PK ? K / 4 : 1];
 #pragma unroll
         for (int w = 0; w < (TR && PK ? K / 4 : 1); ++w) facc[w] = 0;
+        // 16-bit trace codes: the packed constants 1, 2, 4 and 16
+        const uint32_t C1 = TR && PK ? opaque(0x00010001u) : 0u;
+        const uint32_t C2 = TR && PK ? opaque(0x00020002u) : 0u;
+        const uint32_t C4 = TR && PK ? opaque(0x00040004u) : 0u;
+        const uint32_t C16 = TR && PK ? opaque(0x00100010u) : 0u;
         uint8_t *tr_lane = nullptr;
         if constexpr (TR) {
             if (tr_fits && mine && c < tr_chunks)
                 tr_lane = tr_codes + ((int64_t)c * tr_rows * W + l) * kTrRowBytes;
         }
+        // 16-bit cells at 16 columns: a lane's codes of a row are 16 bytes,
+        // and lanes 2k and 2k+1 of one row share a 32-byte sector.  Lane 2k
+        // reaches the row a step before lane 2k+1, so it holds its codes for
+        // one step and the two halves of each sector are stored together.
+        constexpr bool TR_PAIRED = TR && PK && K == 16;
+        uint32_t tr_held[TR_PAIRED ? 4 : 1];
+#pragma unroll
+        for (int w = 0; w < (TR_PAIRED ? 4 : 1); ++w) tr_held[w] = 0;
+        const bool tr_delay = TR_PAIRED && W > 1 && (l & 1) == 0;
         uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
         uint32_t cbest = 0;           // packed (or wide) best row maximum in this chunk
         int32_t crow[NPG];
@@ -1077,11 +1099,11 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         const uint32_t hh = pmax3(dk, f, e) & inband(k);
                         if constexpr (TR) {
                             // H >= the diagonal term and >= E; E >= H(i, j-1) - alpha
-                            const uint32_t nd = pnz(psub(hh, dk));
-                            const uint32_t ne = pnz(psub(hh, e));
-                            const uint32_t ex = pnz(psub(e, ha_left));
-                            const uint32_t nib = pmad(ex, 0x00040004u, pmad(ne, 0x00020002u, nd));
-                            acc[k >> 2] = pmad(acc[k >> 2], 0x00100010u, nib);
+                            const uint32_t nd = pnz(psub(hh, dk), C1);
+                            const uint32_t ne = pnz(psub(hh, e), C1);
+                            const uint32_t ex = pnz(psub(e, ha_left), C1);
+                            const uint32_t nib = pmad(ex, C4, pmad(ne, C2, nd));
+                            acc[k >> 2] = pmad(acc[k >> 2], C16, nib);
                         }
                         dk = dnext;
                         H[k] = hh;
@@ -1089,7 +1111,7 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         F[k] = pmax(psub(f, BE2), ha);
                         if constexpr (TR) {
                             // F(i+1, j) >= H(i, j) - alpha
-                            fnew[k >> 2] = pmad(fnew[k >> 2], 0x00100010u, pnz(psub(F[k], ha)));
+                            fnew[k >> 2] = pmad(fnew[k >> 2], C16, pnz(psub(F[k], ha), C1));
                             ha_left = ha;
                         }
                         e = pmax(psub(e, BE2), ha);
@@ -1103,7 +1125,19 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             acc[w] |= facc[w] << 3;    // bit 0 of each nibble to bit 3
                             facc[w] = fnew[w];
                         }
-                        if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
+                        if constexpr (TR_PAIRED) {
+                            // even lanes store the row before this one (held
+                            // since the last step), odd lanes this row
+                            const int row = tr_delay ? i - 1 : i;
+                            const uint4 v = tr_delay ? make_uint4(tr_held[0], tr_held[1],
+                                                                  tr_held[2], tr_held[3])
+                                                     : make_uint4(acc[0], acc[1], acc[2], acc[3]);
+                            if (tr_lane != nullptr && (uint32_t)row < (uint32_t)tr_rows)
+                                *reinterpret_cast<uint4 *>(tr_lane +
+                                                           (int64_t)row * W * kTrRowBytes) = v;
+#pragma unroll
+                            for (int w = 0; w < 4; ++w) tr_held[w] = acc[w];
+                        } else if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
                             uint8_t *dst = tr_lane + (int64_t)i * W * kTrRowBytes;
                             if constexpr (K == 8) {
                                 *reinterpret_cast<uint2 *>(dst) = make_uint2(acc[0], acc[1]);
@@ -1317,6 +1351,13 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
             } else {
                 run_steps(0, S, std::false_type{}, std::false_type{}, std::false_type{}, std::false_type{});
             }
+        }
+        if constexpr (TR_PAIRED) {
+            // the even lanes' last row, still held
+            const int row = r0 + S - 1 - l;
+            if (tr_delay && tr_lane != nullptr && (uint32_t)row < (uint32_t)tr_rows)
+                *reinterpret_cast<uint4 *>(tr_lane + (int64_t)row * W * kTrRowBytes) =
+                    make_uint4(tr_held[0], tr_held[1], tr_held[2], tr_held[3]);
         }
         if constexpr (!BAND) {
             // ring mode: the column's last, partial block goes to the slot
