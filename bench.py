@@ -92,8 +92,16 @@ def kernel_source_hash(files=("csrc/salo_kernels.hip", "csrc/salo_internal.h",
     import hashlib
     h = hashlib.sha256()
     for f in files:
-        with open(os.path.join(ROOT, "paper_2301_09310_amd", f), "rb") as fh:
-            h.update(fh.read())
+        path = os.path.join(ROOT, "paper_2301_09310_amd", f)
+        if f.endswith(".json"):
+            # a tuning record: only the table the build compiles in counts
+            with open(path) as fh:
+                bins = json.load(fh)["bins"]
+            h.update(json.dumps([[b["m_hi"], b["packed"], b["lanes"], b.get("cols", 0)]
+                                 for b in bins]).encode())
+        else:
+            with open(path, "rb") as fh:
+                h.update(fh.read())
     return h.hexdigest()[:16]
 
 
@@ -1007,10 +1015,16 @@ def serve_bench(args) -> int:
     (its own JSON line; the default mixed-workload line carries the same
     block)."""
     from paper_2301_09310_amd import inputs as I
+    from paper_2301_09310_amd import salo
+    # latency bins: a served launch's requests wait for its longest pair,
+    # which the throughput table's 16-lane groups run four times slower
+    salo.load_tune_table(os.path.join(ROOT, "paper_2301_09310_amd", "tune_gfx950.json"),
+                         "serve_bins")
     t0 = time.time()
     pool = I.mixed(0, args.serve_pool)
     log("serve pool: %d mixed pairs in %.1fs" % (pool.n_pairs, time.time() - t0))
     blk = serve_block(args, pool)
+    blk["bin_table"] = "serve_bins of tune_gfx950.json (latency)"
     p99 = blk["rates"].get("0.8x", next(iter(blk["rates"].values())))["p99_ms"]
     rec = {"metric": METRIC, "value": p99, "unit": "ms (p99 at 0.8x)",
            "n_gpus": 1, "higher_is_better": False, "data": "synthetic", "dtype": "f16x2+u16x2",

@@ -436,12 +436,14 @@ def get_bins():
             for i in range(n.value)]
 
 
-def load_tune_table(path: str) -> None:
-    """Install the bin table of an autotuner JSON file."""
+def load_tune_table(path: str, key: str = "bins") -> None:
+    """Install a bin table of an autotuner JSON file: `bins` (throughput,
+    the built-in default) or `serve_bins` (latency, for served streams).
+    The table applies to every later call in this process."""
     import json
     with open(path) as f:
         t = json.load(f)
-    set_bins([(b["m_hi"], b["packed"], b["lanes"], b.get("cols", 0)) for b in t["bins"]])
+    set_bins([(b["m_hi"], b["packed"], b["lanes"], b.get("cols", 0)) for b in t[key]])
 
 
 def pack_bases(chars, offsets=None, revcomp: bool = False, out=None, invalid=None,
