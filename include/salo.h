@@ -247,7 +247,7 @@ salo_status_t salo_align_batch_banded(const uint8_t *q_seqs, const int64_t *q_of
  * workspace: DEVICE scratch of workspace_bytes, 256-byte aligned, owned by
  * the caller and only used during the call.  Each resident wave (CUs x 8
  * with the default 16 columns per lane, CUs x 12 with opts->cols = 8)
- * gets an equal share; a wave
+ * gets an equal share, at most 1 GiB (bytes past that are not used); a wave
  * aligns up to 64 / W pair groups at once (a group holds two pairs in
  * 16-bit cells or one in 32-bit cells) and each group needs ceil(its
  * longer span / (W x cols)) x W x cols x (its longer span's rows) / 2 bytes

@@ -410,7 +410,10 @@ salo_status_t run_align(const uint8_t *q_seqs, const int64_t *q_offsets,
     p.tag_done = sig.done;
     p.band = band;
     if (trace) {
-        const int64_t slot = (trace->ws_bytes / grid) & ~(int64_t)255;
+        // each resident wave's share, at most 1 GiB (the kernel addresses
+        // a share with 32-bit offsets)
+        const int64_t slot =
+            std::min<int64_t>(trace->ws_bytes / grid, (int64_t)1 << 30) & ~(int64_t)255;
         if (slot < 4096)
             return fail(SALO_ERR_INVALID, "trace workspace below 4 KiB per resident wave (" +
                                               std::to_string(grid) + " waves)");

@@ -74,6 +74,13 @@ __device__ __forceinline__ uint32_t opaque(uint32_t v) {
     asm volatile("" : "+v"(v));
     return v;
 }
+// A value the reassociation pass cannot look into (no instruction): the
+// code word's Horner step acc * 16 + nibble then stays one multiply-add,
+// where distributing the nibble's own sum over it would take four.
+__device__ __forceinline__ uint32_t sealed(uint32_t v) {
+    asm("" : "+v"(v));
+    return v;
+}
 // Maximum of three packed cell pairs.  Cell values stay in [0, 0x7BFF]
 // (kPackedLimit), where reading the bits as binary16 gives finite,
 // non-negative numbers (denormals included, which the kernels keep) in the
@@ -437,9 +444,40 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
     const int64_t cap = P.cig_off[p + 1] - base;
     uint32_t *out = P.cig + base;
     // W and K are powers of two: column j is in chunk j >> log2(W K), lane
-    // (j >> log2 K) & (W - 1), slot j & (K - 1)
+    // (j >> log2 K) & (W - 1), slot j & (K - 1); a 32-bit word holds 4
+    // cells of a row (16-bit cells, this pair's half) or 8 (32-bit cells)
     const int lw = __builtin_ctz((unsigned)W), lk = __builtin_ctz((unsigned)K);
+    constexpr int kPerWord = PKD ? 4 : 8;
+    auto word_at = [&](int r, int c) -> uint32_t {
+        const int ch = c >> (lw + lk), lq = (c >> lk) & (W - 1), k = c & (K - 1);
+        const int64_t at = ((int64_t)ch * rows + r) * W + lq;
+        return PKD ? reinterpret_cast<const uint32_t *>(codes + at * K)[k >> 2]
+                   : reinterpret_cast<const uint32_t *>(codes + at * (K / 2))[k >> 3];
+    };
     int i = pr.n - 1, j = pr.m - 1, state = 0;   // 0: H, 1: E, 2: F
+    // the code word of cell (i, j), and the packed bases at q0 + j and t0 + i
+    // with the words before them already requested (the walk goes up and
+    // left, so a word's bases are used on consecutive steps)
+    uint32_t cw = word_at(i, j);
+    int64_t qp = pr.q0 + j, tp = pr.t0 + i;
+    uint32_t qcur = qs.word(qp >> 4), qprv = qs.word((qp >> 4) - 1);
+    uint32_t tcur = ts.word(tp >> 4), tprv = ts.word((tp >> 4) - 1);
+    auto left = [&]() {
+        if ((qp & 15) == 0) {
+            qcur = qprv;
+            qprv = qs.word((qp >> 4) - 2);
+        }
+        --qp;
+        --j;
+    };
+    auto up = [&]() {
+        if ((tp & 15) == 0) {
+            tcur = tprv;
+            tprv = ts.word((tp >> 4) - 2);
+        }
+        --tp;
+        --i;
+    };
     uint32_t run_op = 0, run_len = 0;
     int64_t nruns = 0;
     bool ok = true;
@@ -449,45 +487,35 @@ __device__ void trace_walk(const KParams &P, const PairRef &pr, uint64_t key,
             ok = false;
             break;
         }
-        const int c = j >> (lw + lk), lq = (j >> lk) & (W - 1), k = j & (K - 1);
-        // in state H the step may be an aligned pair: fetch both bases with
-        // the code, so the three loads overlap
-        const int64_t qp = pr.q0 + j, tp = pr.t0 + i;
-        uint32_t qword = 0, tword = 0;
-        if (state == 0) {
-            qword = qs.word(qp >> 4);
-            tword = ts.word(tp >> 4);
-        }
-        uint32_t nib;
-        if constexpr (PKD) {
-            const uint32_t w = *reinterpret_cast<const uint32_t *>(
-                codes + (((int64_t)c * rows + i) * W + lq) * K + 4 * (k >> 2));
-            nib = (w >> (16 * half + 4 * (3 - (k & 3)))) & 15u;
-        } else {
-            const uint8_t byte = codes[(((int64_t)c * rows + i) * W + lq) * (K / 2) + (k >> 1)];
-            nib = (byte >> ((k & 1) * 4)) & 15u;
-        }
+        const uint32_t nib = PKD ? (cw >> (16 * half + 4 * (3 - (j & 3)))) & 15u
+                                 : (cw >> (4 * (j & 7))) & 15u;
         uint32_t op;
         bool done = false;
         if (state == 0) {
+            // a gap state starts at this same cell: keep its word
             if (nib & 1u) {
                 state = (nib & 2u) ? 2 : 1;
                 continue;
             }
-            const uint32_t qb = (qword >> (2 * (qp & 15))) & 3u;
-            const uint32_t tb = (tword >> (2 * (tp & 15))) & 3u;
+            const uint32_t qb = (qcur >> (2 * (qp & 15))) & 3u;
+            const uint32_t tb = (tcur >> (2 * (tp & 15))) & 3u;
             op = qb == tb ? kOpEq : kOpX;
             done = i == 0 && j == 0;
-            --i;
-            --j;
+            left();
+            up();
+            if (!done && i >= 0 && j >= 0) cw = word_at(i, j);
         } else if (state == 1) {
             op = kOpI;
             if (!((nib >> 2) & 1u)) state = 0;
-            --j;
+            // the same word unless j was its first cell
+            const bool same = (j & (kPerWord - 1)) != 0;
+            left();
+            if (!same && j >= 0) cw = word_at(i, j);
         } else {
             op = kOpD;
             if (!((nib >> 3) & 1u)) state = 0;
-            --i;
+            up();
+            if (i >= 0) cw = word_at(i, j);
         }
         if (op == run_op) {
             ++run_len;
@@ -654,9 +682,12 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
     // pairs share K bytes per lane and row, over the larger pair's chunks
     // and rows)
     uint8_t *tr_codes = nullptr;
+    uint8_t *tr_wave = nullptr;    // the wave's code slot (at most 1 GiB)
+    uint32_t tr_goff = 0;          // this group's share in it
     bool tr_fits = false;
     int tr_chunks = 0, tr_rows = 0;
     constexpr int kTrRowBytes = PK ? K : K / 2;
+    const int tr_stride = W * kTrRowBytes;   // bytes from one row to the next
     if constexpr (TR) {
         const int64_t gslot = (P.trace_slot / G) & ~(int64_t)15;
         int mg = 0;
@@ -667,7 +698,9 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         }
         tr_chunks = (mg + W * K - 1) / (W * K);
         tr_fits = (int64_t)tr_chunks * W * tr_rows * kTrRowBytes <= gslot;
-        tr_codes = P.trace_ws + (int64_t)blockIdx.x * P.trace_slot + (int64_t)g * gslot;
+        tr_wave = P.trace_ws + (int64_t)blockIdx.x * P.trace_slot;
+        tr_goff = (uint32_t)(g * gslot);
+        tr_codes = tr_wave + tr_goff;
     }
     // slot byte offsets: row r of this lane's group is at (r & rwrap) *
     // row_bytes + ld_lane; a row past the rows the previous chunk wrote
@@ -810,11 +843,6 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         const uint32_t C2 = TR && PK ? opaque(0x00020002u) : 0u;
         const uint32_t C4 = TR && PK ? opaque(0x00040004u) : 0u;
         const uint32_t C16 = TR && PK ? opaque(0x00100010u) : 0u;
-        uint8_t *tr_lane = nullptr;
-        if constexpr (TR) {
-            if (tr_fits && mine && c < tr_chunks)
-                tr_lane = tr_codes + ((int64_t)c * tr_rows * W + l) * kTrRowBytes;
-        }
         // 16-bit cells at 16 columns: a lane's codes of a row are 16 bytes,
         // and lanes 2k and 2k+1 of one row share a 32-byte sector.  Lane 2k
         // reaches the row a step before lane 2k+1, so it holds its codes for
@@ -824,6 +852,22 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
 #pragma unroll
         for (int w = 0; w < (TR_PAIRED ? 4 : 1); ++w) tr_held[w] = 0;
         const bool tr_delay = TR_PAIRED && W > 1 && (l & 1) == 0;
+        const uint32_t tr_dmask = tr_delay ? ~0u : 0u;
+        // the row a lane stores at step s is i - delay = r0 + s - l - delay,
+        // at tr_wave + tr_goff + (chunk, lane offset) + row * tr_stride: a
+        // wave-uniform part that moves with s, and a 32-bit lane part made
+        // non-negative by W + 1 rows taken from the uniform part
+        bool tr_on = false;
+        uint32_t tr_loff = 0;
+        if constexpr (TR) {
+            tr_on = tr_fits && mine && c < tr_chunks;
+            tr_loff = tr_goff + ((uint32_t)c * (uint32_t)tr_rows * (uint32_t)W + (uint32_t)l) *
+                                    (uint32_t)kTrRowBytes +
+                      (uint32_t)(r0 - l - (tr_delay ? 1 : 0) + W + 1) * (uint32_t)tr_stride;
+        }
+        auto tr_dst = [&](int s) -> uint8_t * {
+            return tr_wave + (int64_t)(s - W - 1) * tr_stride + tr_loff;
+        };
         uint32_t hout = 0, eout = 0;  // outputs of this lane's last processed row
         uint32_t cbest = 0;           // packed (or wide) best row maximum in this chunk
         int32_t crow[NPG];
@@ -1078,17 +1122,10 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     // step, as in the binary16 loop
                     uint32_t dk = psub(padd(hd, __builtin_amdgcn_perm(TB, TA, SEL[0])), NB2);
                     // trace pass: code words of this row, and the F bits
-                    // for the next one
-                    uint32_t acc[TR ? K / 4 : 1], fnew[TR ? K / 4 : 1];
+                    // for the next one (each word starts at its first cell)
+                    uint32_t acc[TR ? K / 4 : 1] = {}, fnew[TR ? K / 4 : 1] = {};
                     uint32_t ha_left = 0;          // H(i, j-1) - alpha
-                    if constexpr (TR) {
-#pragma unroll
-                        for (int w = 0; w < K / 4; ++w) {
-                            acc[w] = 0;
-                            fnew[w] = 0;
-                        }
-                        ha_left = psub(hin, AL2);
-                    }
+                    if constexpr (TR) ha_left = psub(hin, AL2);
 #pragma unroll
                     for (int k = 0; k < K; ++k) {
                         const uint32_t dnext =
@@ -1102,8 +1139,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             const uint32_t nd = pnz(psub(hh, dk), C1);
                             const uint32_t ne = pnz(psub(hh, e), C1);
                             const uint32_t ex = pnz(psub(e, ha_left), C1);
-                            const uint32_t nib = pmad(ex, C4, pmad(ne, C2, nd));
-                            acc[k >> 2] = pmad(acc[k >> 2], C16, nib);
+                            const uint32_t nib = sealed(pmad(ex, C4, pmad(ne, C2, nd)));
+                            acc[k >> 2] = (k & 3) ? pmad(acc[k >> 2], C16, nib) : nib;
                         }
                         dk = dnext;
                         H[k] = hh;
@@ -1111,7 +1148,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                         F[k] = pmax(psub(f, BE2), ha);
                         if constexpr (TR) {
                             // F(i+1, j) >= H(i, j) - alpha
-                            fnew[k >> 2] = pmad(fnew[k >> 2], C16, pnz(psub(F[k], ha), C1));
+                            const uint32_t fx = pnz(psub(F[k], ha), C1);
+                            fnew[k >> 2] = (k & 3) ? pmad(fnew[k >> 2], C16, fx) : fx;
                             ha_left = ha;
                         }
                         e = pmax(psub(e, BE2), ha);
@@ -1129,16 +1167,17 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                             // even lanes store the row before this one (held
                             // since the last step), odd lanes this row
                             const int row = tr_delay ? i - 1 : i;
-                            const uint4 v = tr_delay ? make_uint4(tr_held[0], tr_held[1],
-                                                                  tr_held[2], tr_held[3])
-                                                     : make_uint4(acc[0], acc[1], acc[2], acc[3]);
-                            if (tr_lane != nullptr && (uint32_t)row < (uint32_t)tr_rows)
-                                *reinterpret_cast<uint4 *>(tr_lane +
-                                                           (int64_t)row * W * kTrRowBytes) = v;
+                            const uint4 v = make_uint4(
+                                (tr_held[0] & tr_dmask) | (acc[0] & ~tr_dmask),
+                                (tr_held[1] & tr_dmask) | (acc[1] & ~tr_dmask),
+                                (tr_held[2] & tr_dmask) | (acc[2] & ~tr_dmask),
+                                (tr_held[3] & tr_dmask) | (acc[3] & ~tr_dmask));
+                            if (tr_on && (uint32_t)row < (uint32_t)tr_rows)
+                                *reinterpret_cast<uint4 *>(tr_dst(s)) = v;
 #pragma unroll
                             for (int w = 0; w < 4; ++w) tr_held[w] = acc[w];
-                        } else if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
-                            uint8_t *dst = tr_lane + (int64_t)i * W * kTrRowBytes;
+                        } else if (tr_on && (uint32_t)i < (uint32_t)tr_rows) {
+                            uint8_t *dst = tr_dst(s);
                             if constexpr (K == 8) {
                                 *reinterpret_cast<uint2 *>(dst) = make_uint2(acc[0], acc[1]);
                             } else {
@@ -1183,8 +1222,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
                     }
                     if constexpr (TR) {
                         fbits = fnext;
-                        if (tr_lane != nullptr && (uint32_t)i < (uint32_t)tr_rows) {
-                            uint8_t *dst = tr_lane + (int64_t)i * W * kTrRowBytes;
+                        if (tr_on && (uint32_t)i < (uint32_t)tr_rows) {
+                            uint8_t *dst = tr_dst(s);
                             if constexpr (K == 8) {
                                 *reinterpret_cast<uint32_t *>(dst) = code[0];
                             } else if constexpr (K == 16) {
@@ -1355,8 +1394,8 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         if constexpr (TR_PAIRED) {
             // the even lanes' last row, still held
             const int row = r0 + S - 1 - l;
-            if (tr_delay && tr_lane != nullptr && (uint32_t)row < (uint32_t)tr_rows)
-                *reinterpret_cast<uint4 *>(tr_lane + (int64_t)row * W * kTrRowBytes) =
+            if (tr_delay && tr_on && (uint32_t)row < (uint32_t)tr_rows)
+                *reinterpret_cast<uint4 *>(tr_dst(S)) =
                     make_uint4(tr_held[0], tr_held[1], tr_held[2], tr_held[3]);
         }
         if constexpr (!BAND) {
@@ -1403,15 +1442,31 @@ __device__ __forceinline__ void run_unit(const KParams &P, BaseStream qs, BaseSt
         __builtin_amdgcn_wave_barrier();
     }
 
+    if constexpr (TR) {
+        // one walker per pair: lane h of the group walks pair h, so the
+        // group's two pairs walk at the same time (a one-lane group walks
+        // them one after the other)
+        uint64_t keys[NPG];
+#pragma unroll
+        for (int h = 0; h < NPG; ++h) keys[h] = group_max_u64(best[h].key(), W);
+        if (W > 1) {
+            if (mine && l < NPG) {
+                const bool second = NPG > 1 && l == 1;
+                trace_walk<K, PK>(P, second ? pr[NPG - 1] : pr[0],
+                                  second ? keys[NPG - 1] : keys[0], tr_codes, tr_fits, W,
+                                  second ? 1 : 0, tr_rows, qs, ts);
+            }
+        } else if (mine) {
+#pragma unroll
+            for (int h = 0; h < NPG; ++h)
+                trace_walk<K, PK>(P, pr[h], keys[h], tr_codes, tr_fits, W, h, tr_rows, qs, ts);
+        }
+        return;
+    }
 #pragma unroll
     for (int h = 0; h < NPG; ++h) {
         const uint64_t key = group_max_u64(best[h].key(), W);
-        if constexpr (TR) {
-            // one walker per pair: lane h of the group (lane 0 for both
-            // pairs of a one-lane group)
-            if (mine && l == (W > 1 ? h : 0))
-                trace_walk<K, PK>(P, pr[h], key, tr_codes, tr_fits, W, h, tr_rows, qs, ts);
-        } else if constexpr (SPL) {
+        if constexpr (SPL) {
             // the strips' bests merge in the workgroup (split_kernel)
             if (lane == 0) sp->keys[sp->ws * 2 + h] = key;
         } else {
