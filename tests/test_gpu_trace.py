@@ -2,7 +2,9 @@
 bit: every pair's CIGAR runs and run count, for the GPU's own answers and
 starts (themselves checked against the oracles), across scorings with and
 without gap-open ties, both column counts, forced lane-group widths, long
-spans, the hand-derived fixtures and a workspace too small for some pairs."""
+spans, the hand-derived fixtures and a workspace too small for some pairs;
+and the starts and CIGARs of every pair of the 2M-pair short-read batch
+against the oracle's stored digests."""
 import os
 
 import numpy as np
@@ -202,3 +204,54 @@ def test_trace_on_side_stream(dev):
     for p in np.nonzero(wln > 0)[0]:
         a, n = woff[p], wln[p]
         assert np.array_equal(g[a:a + n], wcig[a:a + n]), p
+
+
+def test_short_reads_every_pair_digest(dev):
+    """Start positions and CIGARs of EVERY pair of the benchmark's short-read
+    batch (2,000,000 pairs) against the oracle's, stored as digests in
+    tests/golden/trace_digests.json by tests/golden/make_trace_digests.py
+    (oracle and seeded generator only).  On a mismatch the chunk digests name
+    the first 65,536-pair chunk that differs, and the oracle runs on its
+    first 2,000 pairs to report the first differing pair."""
+    import json
+    import sys
+    import torch
+    from paper_2301_09310_amd import salo
+    sys.path.insert(0, os.path.join(HERE, "golden"))
+    import make_trace_digests as D
+    with open(os.path.join(HERE, "golden", "trace_digests.json")) as f:
+        want = json.load(f)["short_reads"]
+    b = I.short_reads(0)
+    assert b.sha256() == want["dataset_sha256"], "the generator changed; rerun the script"
+    _say("short_reads every pair", b.n_pairs)
+    q, qo, t, to = salo.to_device(b)
+    ans = salo.align_batch(q, qo, t, to)
+    st = salo.align_starts(q, qo, t, to, ans)
+    off, cig, ln = salo.align_trace(q, qo, t, to, ans, st, workspace_bytes=16 << 30)
+    torch.cuda.synchronize()
+    assert salo.error_count() == 0
+    qs, ts = (x.cpu().numpy().astype(np.int64) for x in st)
+    off, cig, ln = off.cpu().numpy(), cig.cpu().numpy().view(np.uint32), ln.cpu().numpy()
+    del q, qo, t, to, ans, st
+    torch.cuda.empty_cache()
+    runs, starts = D.packed_runs(off, cig, ln)
+    got = D.trace_digests(qs, ts, ln, runs, starts, want["chunk_pairs"])
+    if all(got[k] == want[k] for k in ("q_start", "t_start", "cigar_len", "cigar_runs")):
+        return
+    bad = next(i for i, (g, w) in enumerate(zip(got["chunks"], want["chunks"])) if g != w)
+    c0 = bad * want["chunk_pairs"]
+    idx = np.arange(c0, min(b.n_pairs, c0 + 2000))
+    sub = b.subset(idx)
+    w_ans = O.align_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets)
+    w_st = O.start_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, *w_ans)
+    woff, wcig, wln = O.trace_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets,
+                                    w_ans[0], w_st[0], w_ans[1], w_st[1], w_ans[2])
+    for k, p in enumerate(idx):
+        same = (qs[p] == w_st[0][k] and ts[p] == w_st[1][k] and ln[p] == wln[k] and
+                np.array_equal(cig[off[p]:off[p] + max(ln[p], 0)],
+                               wcig[woff[k]:woff[k] + max(wln[k], 0)]))
+        if not same:
+            raise AssertionError("pair %d: gpu start (%d, %d) %s, oracle start (%d, %d) %s" % (
+                p, qs[p], ts[p], O.cigar_string(cig, off[p], ln[p]), w_st[0][k], w_st[1][k],
+                O.cigar_string(wcig, woff[k], wln[k])))
+    raise AssertionError("chunk %d differs, but not in its first %d pairs" % (bad, len(idx)))
