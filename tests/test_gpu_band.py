@@ -2,8 +2,8 @@
 oracle (Eq. 1 restricted to |i - j| <= band), bit for bit: scores and end
 positions, over band widths from 0 to wider than every pair, every lane-group
 width and column count, every cell type, the boundary ring of long targets,
-and sampled pairs of the anchored long workload at the benchmark's launch
-configuration."""
+and every pair of the anchored long workload at the benchmark's launch
+configuration (against the band oracle's stored digests)."""
 import numpy as np
 import pytest
 
@@ -134,3 +134,48 @@ def test_band_validation(dev):
         salo.align_banded(q, qo, t, to, -1)
     with pytest.raises(salo.SaloError):
         salo.align_banded(q, qo, t, to, 5, mode="plain")
+
+
+def test_anchored_long_every_pair_digest(dev):
+    """EVERY pair of the benchmark's banded workload (200,000 anchored pairs,
+    band 100, default options) against the band oracle's answers, stored as
+    digests in tests/golden/band_digests.json by
+    tests/golden/make_band_digests.py (oracle and seeded generator only).  On
+    a mismatch the chunk digests name the first 65,536-pair chunk that
+    differs, and the oracle runs on its first 500 pairs to report the first
+    differing pair."""
+    import hashlib
+    import json
+    import os
+    import torch
+    from paper_2301_09310_amd import salo
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "band_digests.json")) as f:
+        want = json.load(f)["anchored_long_band100"]
+    b = I.anchored_long(0, want["pairs"])
+    assert b.sha256() == want["dataset_sha256"], "the generator changed; rerun the script"
+    _say("anchored_long every pair, band", want["band"])
+    q, qo, t, to = salo.to_device(b)
+    out = salo.align_banded(q, qo, t, to, want["band"])
+    torch.cuda.synchronize()
+    assert salo.error_count() == 0
+    got = tuple(x.cpu().numpy() for x in out)
+    del q, qo, t, to, out
+    torch.cuda.empty_cache()
+    dig = lambda a: hashlib.sha256(np.ascontiguousarray(a, dtype="<i4").tobytes()).hexdigest()
+    if all(dig(g) == want[k] for g, k in zip(got, ("score", "q_end", "t_end"))):
+        return
+    chunk = want["chunk_pairs"]
+    for c, wd in enumerate(want["chunks"]):
+        h = hashlib.sha256()
+        for a in got:
+            h.update(np.ascontiguousarray(a[c * chunk:(c + 1) * chunk], dtype="<i4").tobytes())
+        if h.hexdigest() != wd:
+            break
+    idx = np.arange(c * chunk, min(b.n_pairs, c * chunk + 500))
+    sub = b.subset(idx)
+    w = O.align_banded(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets, want["band"])
+    for k, p in enumerate(idx):
+        g3, w3 = tuple(int(x[p]) for x in got), tuple(int(x[k]) for x in w)
+        assert g3 == w3, "pair %d: gpu %s, oracle %s" % (p, g3, w3)
+    raise AssertionError("chunk %d differs, but not in its first %d pairs" % (c, len(idx)))
