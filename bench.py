@@ -207,16 +207,27 @@ def cpu_baseline(O, batch, workload, masks_np, all_cells: float, one_cells: floa
     return out
 
 
-def full_parity(batch, workload, n_pairs_default, got):
+def full_parity(batch, workload, n_pairs_default, got, masks=None, n_fraction=0.0):
     """Digest comparison of every pair's answers with the oracle's answers
-    stored in tests/golden/full_digests.json (written by a script that runs
-    only the oracle and the generator); None when the batch has none."""
+    stored in tests/golden/full_digests.json, or, for a batch with N masks,
+    tests/golden/n_digests.json (both written by scripts that run only the
+    oracle and the generators); None when the batch has none."""
     import hashlib
-    path = os.path.join(ROOT, "tests", "golden", "full_digests.json")
+    sha = lambda a, dt: hashlib.sha256(np.ascontiguousarray(a, dtype=dt).tobytes()).hexdigest()
+    name = "n_digests.json" if masks is not None else "full_digests.json"
+    path = os.path.join(ROOT, "tests", "golden", name)
     if not os.path.exists(path) or batch.n_pairs != n_pairs_default:
         return None
     with open(path) as f:
-        rec = json.load(f).get(workload)
+        table = json.load(f)
+    if masks is None:
+        rec = table.get(workload)
+    else:
+        rec = next((r for k, r in table.items() if k.startswith(workload + "_n")
+                    and isinstance(r, dict) and r.get("n_fraction") == n_fraction), None)
+        if rec is not None and (sha(masks[0], "<u4") != rec["q_nmask"] or
+                                sha(masks[1], "<u4") != rec["t_nmask"]):
+            return None
     if rec is None or rec.get("dataset_sha256") != batch.sha256():
         return None
     ok = True
@@ -362,15 +373,8 @@ def main(argv=None) -> int:
     q_nmask = t_nmask = None
     masks_np = (None, None)
     if args.n_fraction > 0:
-        rng_n = np.random.default_rng([0, 99])
-
-        def n_mask(total):
-            bits = rng_n.random(total) < args.n_fraction
-            words = np.zeros(max((total + 31) // 32, 1), np.uint32)
-            idx = np.nonzero(bits)[0]
-            np.bitwise_or.at(words, idx >> 5, np.uint32(1) << (idx & 31).astype(np.uint32))
-            return words
-        masks_np = (n_mask(int(batch.q_offsets[-1])), n_mask(int(batch.t_offsets[-1])))
+        masks_np = I.random_n_masks(int(batch.q_offsets[-1]), int(batch.t_offsets[-1]),
+                                    args.n_fraction, 0)
         q_nmask = torch.from_numpy(masks_np[0].view(np.int32)).to(dev)
         t_nmask = torch.from_numpy(masks_np[1].view(np.int32)).to(dev)
     out = tuple(torch.empty(n, dtype=torch.int32, device=dev) for _ in range(3))
@@ -437,8 +441,8 @@ def main(argv=None) -> int:
 
     # every pair's answers against the oracle's stored digests
     got_all = [x.cpu().numpy() for x in out]
-    full_ok = full_parity(batch, args.workload, default_pairs, got_all) \
-        if q_nmask is None else None
+    full_ok = full_parity(batch, args.workload, default_pairs, got_all,
+                          masks_np if q_nmask is not None else None, args.n_fraction)
     if full_ok is not None:
         log("every pair vs the oracle's digests: %s" % ("bit-exact" if full_ok else "MISMATCH"))
 

@@ -425,6 +425,23 @@ def mixed_lengths(rng, n):
     return np.where(u < 0.60, a, np.where(u < 0.95, b, c)).astype(np.int64)
 
 
+def random_n_masks(q_total: int, t_total: int, fraction: float, seed: int = 0):
+    """Seeded N masks for a batch's two streams: each base is marked N with
+    probability `fraction`, drawn for the query stream first and then for
+    the target stream from one generator.  Returns two uint32 arrays of one
+    bit per base (bit k of word k >> 5), the layout the N-mask calls take."""
+    rng = np.random.default_rng([seed, 99])
+
+    def one(total):
+        bits = rng.random(total) < fraction
+        words = np.zeros(max((total + 31) // 32, 1), np.uint32)
+        idx = np.nonzero(bits)[0]
+        np.bitwise_or.at(words, idx >> 5, np.uint32(1) << (idx & 31).astype(np.uint32))
+        return words
+    qm = one(int(q_total))
+    return qm, one(int(t_total))
+
+
 def random_pairs(seed: int, n_pairs: int, max_len: int, min_len: int = 0,
                  related: float = 0.5) -> Batch:
     """Fuzz workload: independent lengths U{min_len..max_len}; a fraction of

@@ -145,3 +145,48 @@ def test_pack_n_mask_then_align(dev):
         want = O.align_batch(wq, qo, wt, to, q_nmask=wqm, t_nmask=wtm)
         for g, w in zip(ans, want):
             assert np.array_equal(g.cpu().numpy().astype(np.int64), w)
+
+
+def test_short_reads_with_n_every_pair_digest(dev):
+    """EVERY pair of the benchmark's short-read batch with 1% of the bases of
+    both streams marked N (inputs.random_n_masks, the masks bench.py
+    --n-fraction 0.01 uses) against the oracle's answers, stored as digests
+    in tests/golden/n_digests.json by tests/golden/make_n_digests.py (oracle
+    and seeded generators only).  On a mismatch the chunk digests name the
+    first 65,536-pair chunk that differs (the other tests of this file
+    compare pair by pair)."""
+    import hashlib
+    import json
+    import os
+    import torch
+    from paper_2301_09310_amd import salo
+    here = os.path.dirname(os.path.abspath(__file__))
+    with open(os.path.join(here, "golden", "n_digests.json")) as f:
+        want = json.load(f)["short_reads_n001"]
+    b = I.short_reads(0)
+    assert b.sha256() == want["dataset_sha256"], "the generator changed; rerun the script"
+    qm, tm = I.random_n_masks(int(b.q_offsets[-1]), int(b.t_offsets[-1]),
+                              want["n_fraction"], want["n_seed"])
+    sha = lambda a, dt: hashlib.sha256(np.ascontiguousarray(a, dtype=dt).tobytes()).hexdigest()
+    assert sha(qm, "<u4") == want["q_nmask"] and sha(tm, "<u4") == want["t_nmask"]
+    _say("short_reads with N, every pair", b.n_pairs)
+    q, qo, t, to = salo.to_device(b)
+    qmd = torch.from_numpy(qm.view(np.int32)).cuda()
+    tmd = torch.from_numpy(tm.view(np.int32)).cuda()
+    out = salo.align_batch(q, qo, t, to, q_nmask=qmd, t_nmask=tmd)
+    torch.cuda.synchronize()
+    assert salo.error_count() == 0
+    got = tuple(x.cpu().numpy() for x in out)
+    del q, qo, t, to, out, qmd, tmd
+    torch.cuda.empty_cache()
+    if all(sha(g, "<i4") == want[k] for g, k in zip(got, ("score", "q_end", "t_end"))):
+        return
+    chunk = want["chunk_pairs"]
+    for c, wd in enumerate(want["chunks"]):
+        h = hashlib.sha256()
+        for a in got:
+            h.update(np.ascontiguousarray(a[c * chunk:(c + 1) * chunk], dtype="<i4").tobytes())
+        if h.hexdigest() != wd:
+            break
+    raise AssertionError("chunk %d (pairs %d..) differs from the oracle's digest"
+                         % (c, c * chunk))
