@@ -1,13 +1,14 @@
 #!/usr/bin/env python3
 """Write tests/golden/trace_digests.json: the oracle's start positions and
-CIGAR traces for EVERY pair of the short-read workload, as sha256 digests.
+CIGAR traces for EVERY pair of a batch workload (short_reads by default,
+or long_uneven), as sha256 digests.
 
 This script calls only the CPU oracle (oracle/) and the seeded input
 generator (paper_2301_09310_amd/inputs.py, which holds no alignment
 arithmetic).  Nothing here runs or reads the GPU path.
 
-What is stored for short_reads (2,000,000 pairs, seed 0, scoring
-(1, -4, 6, 1)):
+What is stored per workload (short_reads: 2,000,000 pairs; long_uneven:
+200,000; seed 0, scoring (1, -4, 6, 1)):
   * dataset_sha256 -- Batch.sha256() of the generated batch;
   * q_start / t_start -- sha256 of each start array as little-endian int32
     (the latest optimal start of each best alignment, Section II-A);
@@ -19,9 +20,10 @@ What is stored for short_reads (2,000,000 pairs, seed 0, scoring
     be narrowed to a few thousand pairs;
   * checksums -- plain sums (a second, readable check).
 
-About four minutes on eight cores (the start oracle runs on one thread).
+About four minutes on eight cores for short_reads and twenty for
+long_uneven (the start oracle runs on ranges of pairs in parallel).
 
-Usage: python tests/golden/make_trace_digests.py [--threads N]
+Usage: python tests/golden/make_trace_digests.py [--workload NAME] [--threads N]
 """
 from __future__ import annotations
 
@@ -80,20 +82,40 @@ def trace_digests(qs, ts, ln, runs, starts, chunk=CHUNK):
     }
 
 
+def starts_in_ranges(b, ans, threads):
+    """The start oracle over contiguous ranges of pairs on worker threads
+    (each call releases the interpreter lock), in pair order."""
+    from concurrent.futures import ThreadPoolExecutor
+    cuts = np.linspace(0, b.n_pairs, max(1, threads) * 4 + 1).astype(np.int64)
+
+    def run(k):
+        idx = np.arange(cuts[k], cuts[k + 1])
+        if idx.size == 0:
+            return np.zeros(0, np.int64), np.zeros(0, np.int64)
+        sub = b.subset(idx)
+        return O.start_batch(sub.q_seqs, sub.q_offsets, sub.t_seqs, sub.t_offsets,
+                             *(a[idx] for a in ans), scoring=SCORING)
+    with ThreadPoolExecutor(max(1, threads)) as ex:
+        parts = list(ex.map(run, range(len(cuts) - 1)))
+    return tuple(np.concatenate([p[i] for p in parts]) for i in range(2))
+
+
 def main(argv=None) -> int:
     ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="short_reads", choices=("short_reads", "long_uneven"))
     ap.add_argument("--threads", type=int, default=O.default_threads())
     args = ap.parse_args(argv)
     t0 = time.time()
-    b = I.short_reads(0)
-    print("short_reads: %d pairs generated in %.1fs" % (b.n_pairs, time.time() - t0), flush=True)
+    b = I.WORKLOADS[args.workload](0)
+    print("%s: %d pairs generated in %.1fs" % (args.workload, b.n_pairs, time.time() - t0),
+          flush=True)
     secs = {}
     t1 = time.time()
     ans = O.align_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, SCORING,
                         nthreads=args.threads)
     secs["answers"] = round(time.time() - t1, 1)
     t1 = time.time()
-    st = O.start_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, *ans, scoring=SCORING)
+    st = starts_in_ranges(b, ans, args.threads)
     secs["starts"] = round(time.time() - t1, 1)
     t1 = time.time()
     off, cig, ln = O.trace_batch(b.q_seqs, b.q_offsets, b.t_seqs, b.t_offsets, ans[0], st[0],
@@ -107,14 +129,16 @@ def main(argv=None) -> int:
         "oracle_seconds": secs, "oracle_threads": args.threads,
     }
     rec.update(trace_digests(st[0], st[1], ln, runs, starts))
-    table = {
-        "_about": ("Oracle start positions (oracle/start_oracle.c) and CIGAR traces "
-                   "(oracle/trace_oracle.c) of every pair of short_reads, seed 0, scoring %s, "
-                   "as sha256 digests; chunks of %d pairs. Written by "
-                   "tests/golden/make_trace_digests.py (oracle and input generator only)."
-                   % (list(SCORING), CHUNK)),
-        "short_reads": rec,
-    }
+    table = {}
+    if os.path.exists(OUT):
+        with open(OUT) as f:
+            table = json.load(f)
+    table["_about"] = ("Oracle start positions (oracle/start_oracle.c) and CIGAR traces "
+                       "(oracle/trace_oracle.c) of every pair of each workload, seed 0, "
+                       "scoring %s, as sha256 digests; chunks of %d pairs. Written by "
+                       "tests/golden/make_trace_digests.py (oracle and input generator only)."
+                       % (list(SCORING), CHUNK))
+    table[args.workload] = rec
     tmp = OUT + ".tmp"
     with open(tmp, "w") as f:
         json.dump(table, f, indent=1, sort_keys=True)

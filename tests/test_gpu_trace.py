@@ -3,8 +3,8 @@ bit: every pair's CIGAR runs and run count, for the GPU's own answers and
 starts (themselves checked against the oracles), across scorings with and
 without gap-open ties, both column counts, forced lane-group widths, long
 spans, the hand-derived fixtures and a workspace too small for some pairs;
-and the starts and CIGARs of every pair of the 2M-pair short-read batch
-against the oracle's stored digests."""
+and the starts and CIGARs of every pair of the short-read batch against
+the oracle's stored digests."""
 import os
 
 import numpy as np
@@ -206,13 +206,15 @@ def test_trace_on_side_stream(dev):
         assert np.array_equal(g[a:a + n], wcig[a:a + n]), p
 
 
-def test_short_reads_every_pair_digest(dev):
-    """Start positions and CIGARs of EVERY pair of the benchmark's short-read
-    batch (2,000,000 pairs) against the oracle's, stored as digests in
-    tests/golden/trace_digests.json by tests/golden/make_trace_digests.py
-    (oracle and seeded generator only).  On a mismatch the chunk digests name
-    the first 65,536-pair chunk that differs, and the oracle runs on its
-    first 2,000 pairs to report the first differing pair."""
+@pytest.mark.parametrize("workload, ws_gib", [("short_reads", 16)])
+def test_every_pair_digest(dev, workload, ws_gib):
+    """Start positions and CIGARs of EVERY pair of a benchmark batch
+    (short_reads, 2,000,000 pairs) against the oracle's, stored as digests
+    in tests/golden/trace_digests.json by tests/golden/make_trace_digests.py
+    (oracle and seeded generator only), with the workspace the trace
+    benchmark uses.  On a mismatch the chunk
+    digests name the first 65,536-pair chunk that differs, and the oracle
+    runs on its first 2,000 pairs to report the first differing pair."""
     import json
     import sys
     import torch
@@ -220,14 +222,17 @@ def test_short_reads_every_pair_digest(dev):
     sys.path.insert(0, os.path.join(HERE, "golden"))
     import make_trace_digests as D
     with open(os.path.join(HERE, "golden", "trace_digests.json")) as f:
-        want = json.load(f)["short_reads"]
-    b = I.short_reads(0)
+        table = json.load(f)
+    if workload not in table:
+        pytest.skip("no digests stored for %s" % workload)
+    want = table[workload]
+    b = I.WORKLOADS[workload](0)
     assert b.sha256() == want["dataset_sha256"], "the generator changed; rerun the script"
-    _say("short_reads every pair", b.n_pairs)
+    _say(workload, "every pair", b.n_pairs, "workspace GiB", ws_gib)
     q, qo, t, to = salo.to_device(b)
     ans = salo.align_batch(q, qo, t, to)
     st = salo.align_starts(q, qo, t, to, ans)
-    off, cig, ln = salo.align_trace(q, qo, t, to, ans, st, workspace_bytes=16 << 30)
+    off, cig, ln = salo.align_trace(q, qo, t, to, ans, st, workspace_bytes=ws_gib << 30)
     torch.cuda.synchronize()
     assert salo.error_count() == 0
     qs, ts = (x.cpu().numpy().astype(np.int64) for x in st)
